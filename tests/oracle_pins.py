@@ -1,0 +1,214 @@
+"""Pins of the CPU oracle against closed forms, invariants and a library
+routine.  Each check raises AssertionError on failure; the tests call them on
+the real oracle and, with planted mistakes, on mutated copies."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from oracle import density as den
+from oracle import fd, sp2
+from oracle.eig import jacobi_eigh
+import workloads
+
+
+def check_jacobi_2x2(eigh=jacobi_eigh):
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        a, b, c = rng.uniform(-2, 2, 3)
+        h = np.array([[a, b], [b, c]])
+        w, v = eigh(h)
+        r = math.sqrt(((a - c) / 2) ** 2 + b * b)
+        exact = np.array([(a + c) / 2 - r, (a + c) / 2 + r])
+        assert np.allclose(w, exact, atol=1e-14, rtol=0), (w, exact)
+        assert np.allclose(v @ np.diag(w) @ v.T, h, atol=1e-14)
+
+
+def check_jacobi_toeplitz(eigh=jacobi_eigh, n=30, a=0.3, b=-0.7):
+    """Tridiagonal Toeplitz: eigenvalues a + 2b cos(k pi/(n+1)), eigenvectors
+    sin(j k pi/(n+1)) (closed form)."""
+    h = a * np.eye(n) + b * (np.eye(n, k=1) + np.eye(n, k=-1))
+    w, v = eigh(h)
+    k = np.arange(1, n + 1)
+    exact = np.sort(a + 2 * b * np.cos(k * np.pi / (n + 1)))
+    assert np.allclose(w, exact, atol=1e-13, rtol=0), np.abs(w - exact).max()
+    j = np.arange(1, n + 1)
+    # eigenvector of the lowest eigenvalue (b < 0 -> k = 1)
+    u = np.sin(j * 1 * np.pi / (n + 1))
+    u /= np.linalg.norm(u)
+    assert abs(abs(np.dot(u, v[:, 0])) - 1) < 1e-12
+
+
+def check_jacobi_known_spectrum(eigh=jacobi_eigh, n=48):
+    rng = np.random.default_rng(5)
+    lam = np.sort(rng.uniform(-2, 2, n))
+    wl = workloads.make_workload("pin", lam, n // 4, 0.0, 1e-10, 17)
+    w, v = eigh(wl.hp)
+    assert np.allclose(w, lam, atol=1e-13, rtol=0), np.abs(w - lam).max()
+    assert np.allclose(v.T @ v, np.eye(n), atol=1e-13)
+    assert np.allclose((v * w) @ v.T, wl.hp, atol=1e-13)
+
+
+def check_jacobi_vs_lapack(eigh=jacobi_eigh, n=64):
+    rng = np.random.default_rng(9)
+    g = rng.standard_normal((n, n))
+    h = 0.5 * (g + g.T)
+    w, v = eigh(h)
+    wl, vl = np.linalg.eigh(h)
+    assert np.allclose(w, wl, atol=1e-12, rtol=0)
+    # compare spectral projectors of the lowest 20 (robust to eigenvector sign)
+    p = v[:, :20] @ v[:, :20].T
+    pl = vl[:, :20] @ vl[:, :20].T
+    assert np.abs(p - pl).max() < 1e-11
+
+
+def check_density_invariants(density_matrix=den.density_matrix, n=64):
+    wl = workloads.config_workload(0, n=n)
+    d, e, mu, lam = density_matrix(wl.hp, wl.n_occ, 0.0)
+    assert np.linalg.norm(d @ d - d) < 1e-11
+    assert abs(np.trace(d) - wl.n_occ) < 1e-11
+    assert np.linalg.norm(wl.hp @ d - d @ wl.hp) < 1e-11
+    lowest = np.sort(wl.lam)[: int(wl.n_occ)].sum()
+    assert abs(e - lowest) < 1e-11
+    assert abs(den.band_energy(wl.hp, d) - lowest) < 1e-11
+
+
+def check_density_vs_construction(density_matrix=den.density_matrix, n=80, kT=0.0):
+    c = 0 if kT == 0.0 else 2
+    wl = workloads.config_workload(c, n=n)
+    d, e, mu, lam = density_matrix(wl.hp, wl.n_occ, kT)
+    f, mu2 = den.occupations(wl.lam, wl.n_occ, kT)
+    d_ref = (wl.q * f) @ wl.q.T
+    assert np.abs(d - d_ref).max() < 1e-12, np.abs(d - d_ref).max()
+    assert abs(e - float(np.dot(f, wl.lam))) < 1e-11
+    assert abs(mu - mu2) < 1e-9
+
+
+def check_shift_scale_and_permutation(density_matrix=den.density_matrix, n=40):
+    wl = workloads.config_workload(0, n=n)
+    d, *_ = density_matrix(wl.hp, wl.n_occ, 0.0)
+    d2, *_ = density_matrix(2.5 * wl.hp - 0.7 * np.eye(n), wl.n_occ, 0.0)
+    assert np.abs(d - d2).max() < 1e-12
+    perm = np.random.default_rng(3).permutation(n)
+    d3, *_ = density_matrix(wl.hp[np.ix_(perm, perm)], wl.n_occ, 0.0)
+    assert np.abs(d3 - d[np.ix_(perm, perm)]).max() < 1e-12
+
+
+def check_fd_two_level(fermi=den.fermi_dirac, chem=den.chemical_potential):
+    """Two levels at -a and +a with one electron: mu = 0 by symmetry and the
+    occupancies are 1/(1 + exp(-+a/kT)) (the Fermi function of Sec. II.A)."""
+    a, kT = 0.003, 0.0016
+    lam = np.array([-a, a])
+    mu = chem(lam, 1.0, kT)
+    assert abs(mu) < 1e-12
+    f = fermi(lam, mu, kT)
+    exact = 1.0 / (np.exp(lam / kT) + 1.0)
+    assert np.allclose(f, exact, atol=1e-15, rtol=0)
+    # a rotated 2x2: D = f(H) by the 2x2 closed form
+    th = 0.37
+    q = np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]])
+    h = (q * lam) @ q.T
+    d, e, mu3, _ = den.density_matrix(h, 1.0, kT)
+    d_exact = (q * exact) @ q.T
+    assert np.abs(d - d_exact).max() < 1e-14
+    assert abs(e - np.dot(exact, lam)) < 1e-15
+
+
+def check_fd_symmetric_mu(chem=den.chemical_potential):
+    lam = np.linspace(-1, 1, 101)
+    assert abs(chem(lam, 50.5, 0.0016)) < 1e-12
+    lam = np.concatenate([-np.linspace(0.1, 1, 50), np.linspace(0.1, 1, 50)])
+    assert abs(chem(lam, 50.0, 0.01)) < 1e-12
+
+
+def check_fd_low_t_limit(n=64):
+    wl = workloads.config_workload(0, n=n)
+    d0, e0, *_ = den.density_matrix(wl.hp, wl.n_occ, 0.0)
+    d1, e1, *_ = den.density_matrix(wl.hp, wl.n_occ, 1e-4)   # gap 0.2 Ha >> kT
+    assert np.abs(d0 - d1).max() < 1e-12
+    assert abs(e0 - e1) < 1e-11
+
+
+def check_gershgorin(bounds=sp2.gershgorin_bounds):
+    d = np.diag([0.5, -1.25, 3.0, 0.0])
+    assert bounds(d) == (-1.25, 3.0)
+    a, b, c = 0.4, -0.3, 1.1
+    assert np.allclose(bounds(np.array([[a, b], [b, c]])), (a - abs(b), c + abs(b)))
+    h = np.array([[1.0, 0.5, -0.25], [0.5, -2.0, 1.0], [-0.25, 1.0, 0.0]])
+    assert np.allclose(bounds(h), (-3.5, 1.75))
+    wl = workloads.config_workload(1, n=200)
+    lo, hi = bounds(wl.hp)
+    assert lo <= wl.lam.min() and hi >= wl.lam.max()
+
+
+def check_sp2_diagonal(sp2fn=sp2.sp2):
+    """On a diagonal H every eigenvalue follows the scalar maps x -> x^2 or
+    2x - x^2 under the same branch sequence, from (e_max - h)/(e_max - e_min)."""
+    rng = np.random.default_rng(21)
+    n, n_occ = 24, 9
+    lam = np.concatenate([rng.uniform(-1, -0.3, n_occ), rng.uniform(0.1, 1, n - n_occ)])
+    h = np.diag(lam)
+    x, info = sp2fn(h, n_occ, tol=1e-12)
+    lo, hi = lam.min(), lam.max()           # Gershgorin is exact on a diagonal matrix
+    s = (hi - lam) / (hi - lo)
+    for br in info["branches"]:
+        s = s * s if br else 2 * s - s * s
+    assert np.allclose(np.diag(x), s, atol=1e-15, rtol=0)
+    assert np.abs(x - np.diag(np.diag(x))).max() == 0.0
+    assert np.allclose(np.diag(x), (lam < 0).astype(float), atol=1e-6)
+
+
+def check_sp2_matches_definition(sp2fn=sp2.sp2, sizes=(4, 16, 64, 256)):
+    for n in sizes:
+        wl = workloads.config_workload(0, n=n)
+        x, info = sp2fn(wl.hp, wl.n_occ, tol=1e-11)
+        f, _ = den.occupations(wl.lam, wl.n_occ, 0.0)
+        d_ref, e_ref = den.density_from_eig(wl.q, wl.lam, f)
+        assert info["converged"], n
+        assert np.linalg.norm(x - d_ref) < 1e-10, (n, np.linalg.norm(x - d_ref))
+        assert abs(den.band_energy(wl.hp, x) - e_ref) < 1e-10
+        assert abs(np.trace(x) - wl.n_occ) < 1e-10
+
+
+def check_mcweeny(mcw=sp2.mcweeny):
+    x = np.diag([0.02, 0.97, 0.999, 0.0, 1.0, 0.05])
+    y, steps, hist = mcw(x.copy(), 1e-12)
+    s = np.diag(x).copy()
+    for _ in range(steps):
+        s = 3 * s ** 2 - 2 * s ** 3
+    assert np.allclose(np.diag(y), s, atol=1e-15)
+    assert np.allclose(np.diag(y), [0, 1, 1, 0, 1, 0], atol=1e-12)
+
+
+def check_fd_recursion_closed_form(doubling=fd.doubling):
+    lam = np.linspace(-1, 1, 33)
+    mu, beta = 0.013, 625.0
+    m = fd.depth(beta, -1.0, 1.0, mu)
+    d = doubling(np.diag(lam), mu, beta, m)
+    assert np.allclose(np.diag(d), fd.closed_form(lam, mu, beta, m), atol=1e-13, rtol=0)
+    # the closed form tends to the Fermi function: the atanh series gives an
+    # argument error s^3 / (3 * 2^(2m+3)), so |f_m - f| shrinks 4x per step
+    f = den.fermi_dirac(lam, mu, 1.0 / beta)
+    err = [np.abs(fd.closed_form(lam, mu, beta, mm) - f).max() for mm in (m - 2, m - 1, m)]
+    assert err[2] < 2.0 ** -(2 * m + 1), err
+    assert 3.5 < err[0] / err[1] < 4.5 and 3.5 < err[1] / err[2] < 4.5, err
+
+
+def check_fd_recursion_dense(doubling=fd.doubling, n=64):
+    wl = workloads.config_workload(2, n=n)
+    kT = 0.0016
+    f, mu = den.occupations(wl.lam, wl.n_occ, kT)
+    d_ref, _ = den.density_from_eig(wl.q, wl.lam, f)
+    m = fd.depth(1.0 / kT, wl.lam.min(), wl.lam.max(), mu)
+    d = doubling(wl.hp, mu, 1.0 / kT, m)
+    assert np.linalg.norm(d - d_ref) < 1e-11, np.linalg.norm(d - d_ref)
+
+
+ALL_PINS = [
+    check_jacobi_2x2, check_jacobi_toeplitz, check_jacobi_known_spectrum, check_jacobi_vs_lapack,
+    check_density_invariants, check_density_vs_construction, check_shift_scale_and_permutation,
+    check_fd_two_level, check_fd_symmetric_mu, check_fd_low_t_limit, check_gershgorin,
+    check_sp2_diagonal, check_sp2_matches_definition, check_mcweeny,
+    check_fd_recursion_closed_form, check_fd_recursion_dense,
+]

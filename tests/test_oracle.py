@@ -1,0 +1,158 @@
+"""CPU oracle pinned to closed forms, invariants, brute force and a library
+routine (never to itself).  See tests/oracle_pins.py for each pin."""
+import numpy as np
+import pytest
+
+import oracle_pins as pins
+from oracle import density as den
+from oracle import fd, sp2
+
+
+@pytest.mark.parametrize("pin", pins.ALL_PINS, ids=lambda f: f.__name__)
+def test_pin(pin):
+    pin()
+
+
+def test_density_vs_construction_finite_t():
+    pins.check_density_vs_construction(kT=0.0016)
+
+
+def test_sp2_iteration_count_plausible():
+    """Sec. IV reports about 50 SP2 products at its tolerance; a dense rotated
+    band spectrum with Gershgorin bounds needs a similar count here."""
+    import workloads
+    wl = workloads.config_workload(1, n=400)
+    x, info = sp2.sp2(wl.hp, wl.n_occ, tol=1e-8)
+    assert info["converged"]
+    assert 35 <= info["iterations"] <= 65, info["iterations"]
+
+
+def test_reltr_definition():
+    t = [10.0, 12.0, 11.5]
+    assert np.allclose(sp2.rel_trace(t), [0.2, 0.5 / 12.0])
+
+
+# --------------------------------------------------------------------------
+# planted mistakes: each mutant of the oracle must fail at least one pin
+# --------------------------------------------------------------------------
+
+def _fails(fn, *a, **k):
+    try:
+        fn(*a, **k)
+    except AssertionError:
+        return True
+    return False
+
+
+def test_mutant_branch_rule_flipped(monkeypatch):
+    monkeypatch.setattr(sp2, "choose_square",
+                        lambda t, s, n: abs(s - n) > abs(2 * t - s - n))
+    assert _fails(pins.check_sp2_matches_definition, sizes=(16,))
+
+
+def test_mutant_dropped_term_in_update():
+    def bad_sp2(h, n_occ, tol=1e-10, max_iter=100):
+        lo, hi = sp2.gershgorin_bounds(h)
+        x = sp2.initial_iterate(h, lo, hi)
+        br = []
+        for _ in range(max_iter):
+            t, s = np.trace(x), np.sum(x * x)
+            sq = sp2.choose_square(t, s, n_occ)
+            p = x @ x
+            if np.linalg.norm(p - x) <= tol:
+                break
+            br.append(1 if sq else 0)
+            x = p if sq else x - p        # dropped "X +" term
+        return x, dict(branches=br, converged=True)
+    assert _fails(pins.check_sp2_diagonal, sp2fn=bad_sp2)
+
+
+def test_mutant_transposed_eigenbasis():
+    def bad_dm(h, n_occ, kT=0.0):
+        d, e, mu, lam = den.density_matrix(h, n_occ, kT)
+        w, v = np.linalg.eigh(h)
+        f, _ = den.occupations(w, n_occ, kT)
+        return (v.T * f) @ v, e, mu, lam       # Q^T f Q instead of Q f Q^T
+    assert _fails(pins.check_density_vs_construction, density_matrix=bad_dm)
+
+
+def test_mutant_gershgorin_radius_includes_diagonal():
+    def bad_bounds(h):
+        r = np.abs(h).sum(axis=1)
+        return float((np.diag(h) - r).min()), float((np.diag(h) + r).max())
+    assert _fails(pins.check_gershgorin, bounds=bad_bounds)
+
+
+def test_mutant_fermi_missing_half():
+    bad = lambda lam, mu, kT: 0.5 * (1.0 - np.tanh((np.asarray(lam) - mu) / kT))
+    assert _fails(pins.check_fd_two_level, fermi=bad,
+                  chem=lambda lam, n, kT: 0.0)
+
+
+def test_mutant_doubling_wrong_start_scale():
+    def bad(h, mu, beta, m):
+        n = h.shape[0]
+        eye = np.eye(n)
+        y = beta * (h - mu * eye) / 2.0 ** (m + 1)   # wrong power of two
+        for _ in range(m):
+            y = np.linalg.solve(eye + 4.0 * y @ y, 2.0 * y)
+        return 0.5 * eye - y
+    assert _fails(pins.check_fd_recursion_closed_form, doubling=bad)
+
+
+def test_mutant_jacobi_wrong_rotation_sign():
+    def bad_eigh(h):
+        w, v = np.linalg.eigh(h)
+        return w, v[::-1]                              # rows permuted: wrong eigenvectors
+    assert _fails(pins.check_jacobi_2x2, eigh=bad_eigh)
+
+
+# --------------------------------------------------------------------------
+# golden fixtures: the paper's own synthetic matrix (Sec. IV) at N = 8
+# --------------------------------------------------------------------------
+
+def _read_golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    out = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, *v = line.split()
+        out[k] = np.array([float(x) for x in v])
+    return out
+
+
+def test_golden_e1_zero_t():
+    from workloads import paper_e1_matrix
+    g = _read_golden("e1_n8_zero_t.txt")
+    h = paper_e1_matrix(8)
+    # independent check of the stored values with LAPACK
+    w, v = np.linalg.eigh(h)
+    assert np.allclose(g["eigenvalues"], w, atol=1e-13)
+    d = v[:, :7] @ v[:, :7].T
+    assert np.allclose(g["d_diag"], np.diag(d), atol=1e-13)
+    assert np.allclose(g["d_row0"], d[0], atol=1e-13)
+    assert abs(g["band_energy"][0] - w[:7].sum()) < 1e-13
+    # and the oracle reproduces them
+    d2, e2, _, _ = den.density_matrix(h, 7, 0.0)
+    assert abs(e2 - g["band_energy"][0]) < 1e-13
+    x, info = sp2.sp2(h, 7, tol=1e-12)
+    assert np.abs(x - d).max() < 1e-11
+
+
+def test_golden_e1_finite_t():
+    from workloads import paper_e1_matrix
+    g = _read_golden("e1_n8_finite_t.txt")
+    h = paper_e1_matrix(8)
+    w, v = np.linalg.eigh(h)
+    kT = 0.0016
+    mu = g["mu"][0]
+    f = 1.0 / (np.exp((w - mu) / kT) + 1.0)
+    assert abs(f.sum() - 6.8) < 1e-10
+    d = (v * f) @ v.T
+    assert np.allclose(g["d_diag"], np.diag(d), atol=1e-12)
+    assert abs(g["band_energy"][0] - np.dot(f, w)) < 1e-12
+    m = fd.depth(1.0 / kT, w.min(), w.max(), mu, extra=8)
+    dm = fd.doubling(h, mu, 1.0 / kT, m)
+    assert np.abs(dm - d).max() < 1e-11

@@ -1,0 +1,238 @@
+/*
+ * fermidm.h -- C ABI of the MI355X (gfx950) density-matrix library.
+ *
+ * The library turns a dense symmetric projected Hamiltonian Hp (N x N) into
+ * the density matrix D and the band energy Tr(Hp D) without diagonalising
+ * Hp, by recursive Fermi-operator expansion (Khadatkar & Motamarri,
+ * arXiv 2301.04642):
+ *
+ *  - zero temperature (Sec. II.A, D = theta(mu I - Hp)): second-order
+ *    projection (SP2) steps X <- X^2 or X <- 2X - X^2, the branch chosen from
+ *    traces (Sec. II.B.1, Eq. (1); Tr X^2 = ||X||_F^2 as in Sec. III.B),
+ *    started from Gershgorin spectral bounds (Sec. II.C);
+ *  - finite temperature (Sec. II.A, D = [exp(beta(Hp - mu I)) + I]^-1): a
+ *    doubling recursion of projection maps (Sec. II.B.3, Eq. (2)) that
+ *    reproduces the Fermi operator, with mu fixed by Tr D = N_occ;
+ *  - mixed precision (Sec. III.A): the bulk of the products in a lower
+ *    precision, traces, branch decisions and bounds in FP64, and FP64
+ *    refinement at the end.
+ *
+ * Conventions for every entry point:
+ *  - Matrices are float64, row-major, with a leading dimension (in elements)
+ *    ld >= N.  Pointers marked "device" must be device memory of the
+ *    current HIP device; pointers marked "host" are host memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued on it; every call returns only when its results are
+ *    ready (host outputs written, device outputs complete on `stream`).
+ *  - The caller owns every buffer it passes.  The library owns its
+ *    workspace (cached per host thread and device) unless the caller passes
+ *    one in fdm_options.
+ *  - Calls return FDM_OK (0) or a negative status; they never abort.  The
+ *    text of the last error of the calling thread is fdm_last_error().
+ *  - One solve per stream at a time; calls on different streams from
+ *    different host threads are independent.
+ */
+#ifndef FERMIDM_H
+#define FERMIDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define FDM_OK 0
+#define FDM_EINVAL (-1)     /* bad N, ld, n_occ, kT, tol, precision or a null pointer */
+#define FDM_ENOMEM (-2)     /* device allocation failed, or request above a budget    */
+#define FDM_ENOCONV (-3)    /* iteration cap or stagnation: D holds the last iterate   */
+#define FDM_EHIP (-4)       /* a HIP runtime error; see fdm_last_error()               */
+#define FDM_ENONFINITE (-5) /* Hp holds NaN or Inf                                     */
+
+/* ---- precision of the bulk products ------------------------------------ */
+#define FDM_FP64 0    /* every product in FP64 MFMA (the plain method)                     */
+#define FDM_FP32 1    /* FP32 MFMA, FP32 master iterate                                    */
+#define FDM_FP16X3 2  /* X = hi + lo split into two FP16 halves, 3 FP16 MFMA products,
+                         FP32 accumulation (about FP32 accuracy at FP16 MFMA rate)         */
+#define FDM_BF16X3 3  /* as FP16X3 with BF16 halves                                        */
+#define FDM_BF16 4    /* one BF16 MFMA product, FP32 accumulation (reported, not gated)    */
+#define FDM_FP16 5    /* one FP16 MFMA product, FP32 accumulation (reported, not gated)    */
+#define FDM_NPREC 6
+
+/* Options.  Fill with fdm_options_default() and change what you need. */
+typedef struct fdm_options {
+    int32_t precision;      /* FDM_FP64 .. FDM_FP16 (default FDM_FP64)                         */
+    int32_t k64;            /* zero-T mixed forms: SP2 steps done in FP64 before the low-
+                               precision phase; -1 = automatic (default)                       */
+    double tau;             /* zero-T mixed forms: leave the low-precision phase once
+                               ||X^2 - X||_F <= tau; <= 0 = automatic (default)               */
+    int32_t max_iter;       /* SP2 products per phase (default 100)                            */
+    int32_t mcweeny_max;    /* FP64 McWeeny steps in the mixed forms (default 6)               */
+    int32_t max_mu_evals;   /* finite T: Fermi-operator evaluations in the mu search (12)      */
+    int32_t fd_extra_depth; /* finite T: doubling depth = ceil(log2(beta*R)) + this (7)        */
+    int32_t fd_final_fp64;  /* finite T, low precision: finish with one FP64 evaluation (1)    */
+    int32_t validate;       /* 1: reject an Hp that is not symmetric to 1e-12 relative (0)     */
+    int32_t timing;         /* 1: time every product launch with HIP events (0)                */
+    int32_t tile;           /* product tile edge: 0 = automatic, or 64 / 128                   */
+    int32_t reserved;
+    void *workspace;        /* optional caller-owned device memory of workspace_bytes          */
+    size_t workspace_bytes; /* at least fdm_workspace_bytes(N, kT, precision)                  */
+} fdm_options;
+
+/* Per-solve report (host memory, filled by fermi_dm_solve when non-NULL). */
+typedef struct fdm_stats {
+    int32_t status;
+    int32_t iters_fp64_first;   /* zero T: FP64 SP2 products before the low-precision phase   */
+    int32_t iters_low;          /* zero T: low-precision SP2 products                          */
+    int32_t iters_fp64;         /* zero T, FDM_FP64: SP2 products                              */
+    int32_t mcweeny_steps;      /* zero T mixed: FP64 McWeeny steps                            */
+    int32_t mu_evals;           /* finite T: Fermi-operator evaluations                        */
+    int32_t depth;              /* finite T: doubling steps per evaluation                     */
+    int32_t tile;               /* product tile edge used                                       */
+    int32_t products[FDM_NPREC];    /* product launches that ran, per precision                */
+    uint64_t branch_bits[4];    /* SP2 branch of product k (bit k; 1 = X^2), k < 256           */
+    double e_min, e_max;        /* Gershgorin bounds of Hp                                      */
+    double mu;                  /* finite T: chemical potential of D                           */
+    double idempotency;         /* zero T: ||D^2 - D||_F as measured by the last product       */
+    double trace;               /* Tr D                                                         */
+    double band_energy;         /* Tr(Hp D)                                                     */
+    double ms_total;            /* wall time of the call (host clock)                          */
+    double prod_ms[FDM_NPREC];  /* summed duration of product launches (timing = 1)            */
+    double flops[FDM_NPREC];    /* algorithmic flops of the products that ran: N^2 (N+1) each
+                                   (3x for the split forms, which run three products)          */
+} fdm_stats;
+
+/* Fills *opt with the defaults listed above.  Returns FDM_EINVAL if opt is NULL. */
+int fdm_options_default(fdm_options *opt);
+
+/* Device bytes of workspace a solve of size N needs (kT > 0 selects the
+ * finite-temperature solver).  Returns 0 for invalid arguments. */
+size_t fdm_workspace_bytes(int64_t N, double kT, int32_t precision);
+
+/*
+ * fermi_dm_solve -- density matrix of Hp.
+ *
+ *  Hp     device, N x N, leading dimension ldh >= N, symmetric (read only; the
+ *         full matrix is read).
+ *  n_occ  kT == 0: the number of occupied states, an integer in [0, N];
+ *         kT >  0: the electron count Tr D, real in (0, N).
+ *  kT     electronic temperature in Hartree (k_B T_e; beta = 1/kT).  0 selects
+ *         the zero-temperature projector.
+ *  tol    kT == 0: stop when ||X^2 - X||_F <= tol;  kT > 0: stop the mu
+ *         search when |Tr D - n_occ| <= tol (a first-order correction in mu
+ *         follows).  Must be > 0.
+ *  D      device, N x N, leading dimension ldd >= N: receives D (full,
+ *         symmetric).  May not alias Hp.
+ *  E_band host: receives Tr(Hp D) (nullable).
+ *  opt    nullable (defaults).     stats  host, nullable.
+ *
+ * Special cases: n_occ == 0 gives D = 0; n_occ == N at zero temperature
+ * gives D = I.  Returns FDM_ENONFINITE when Hp holds NaN/Inf, FDM_ENOCONV when
+ * the iteration cap is reached or the iteration stagnates (D then holds the
+ * last iterate and stats are filled).
+ */
+int fermi_dm_solve(const double *Hp, int64_t N, int64_t ldh, double n_occ, double kT,
+                   double tol, double *D, int64_t ldd, double *E_band,
+                   const fdm_options *opt, fdm_stats *stats, void *stream);
+
+/* Text for a status code (static storage). */
+const char *fdm_strerror(int code);
+
+/* Text of the calling thread's last error ("" if none). */
+const char *fdm_last_error(void);
+
+/* ---- single steps of the method (for tests and for composing solvers) -- */
+
+/*
+ * fdm_gershgorin -- spectral bounds of Hp by Gershgorin discs (Sec. II.C
+ * needs bounds of the spectrum before the expansion; the paper names no
+ * method): e_min = min_i (H_ii - r_i), e_max = max_i (H_ii + r_i),
+ * r_i = sum_{j != i} |H_ij|.
+ *  H       device, N x N, leading dimension ldh.
+ *  out     host double[4]: e_min, e_max, Tr H, ||H||_F^2.
+ *  nonfinite host int: set to the number of rows holding NaN/Inf (nullable).
+ */
+int fdm_gershgorin(const double *H, int64_t N, int64_t ldh, double *out, int32_t *nonfinite,
+                   void *stream);
+
+/*
+ * fdm_sym_product -- one product of two commuting symmetric matrices with the
+ * fused epilogue of the hot loop (Sec. II.B.1, Eq. (1); Sec. III.B):
+ *
+ *     C = alpha * (A B) + beta * E + gamma * I
+ *
+ * computed on the upper-triangular tiles only and mirrored, so C is exactly
+ * symmetric.  A B is formed in `precision` (the FP16/BF16 forms round A and B
+ * as described for FDM_FP16X3 .. FDM_FP16; the FP16 forms scale by 2^12 and
+ * need |entries| <= 16).  The epilogue and the partial sums run in FP64.
+ *  A, B, E  device, N x N float64, leading dimension ld (E nullable = 0).
+ *  C        device, N x N float64, leading dimension ld; may not alias A/B/E.
+ *  sums     host double[3] (nullable): Tr C, ||C||_F^2, ||A B - E||_F^2.
+ *  tile     0 = automatic, or 64 / 128.
+ * A and B are expected to commute (for X^2, A == B); only their product's
+ * upper triangle is formed.
+ */
+int fdm_sym_product(int32_t precision, const double *A, const double *B, const double *E,
+                    double *C, int64_t N, int64_t ld, double alpha, double beta,
+                    double gamma, double *sums, int32_t tile, void *stream);
+
+/*
+ * fdm_band_energy -- Tr(H D) = sum_ij H_ij D_ij and Tr D in FP64 (the band
+ * energy of Sec. III.C).
+ *  H, D  device, N x N, leading dimensions ldh, ldd.   out host double[2].
+ */
+int fdm_band_energy(const double *H, int64_t ldh, const double *D, int64_t ldd, int64_t N,
+                    double *out, void *stream);
+
+/*
+ * fdm_fermi_operator -- one evaluation of the finite-temperature recursion at
+ * a given mu (Sec. II.B.3, Eq. (2), with the doubling map of the design
+ * notes): Y_0 = (Hp - mu I) / (kT 2^(depth+2)), Y <- 2 Y (I + 4 Y^2)^-1 depth
+ * times (the inverse by Newton-Schulz in `precision`), D = I/2 - Y.
+ *  depth <= 0 selects ceil(log2(beta * max(e_max - mu, mu - e_min))) +
+ *  fd_extra_depth from Gershgorin bounds.
+ *  out host double[3] (nullable): Tr D, Tr(D - D^2), depth used.
+ */
+int fdm_fermi_operator(const double *Hp, int64_t N, int64_t ldh, double mu, double kT,
+                       int32_t depth, int32_t precision, double *D, int64_t ldd, double *out,
+                       void *stream);
+
+/* ---- serving: continuous batching of independent solves --------------- */
+
+typedef struct fdm_server fdm_server;
+
+typedef struct fdm_server_options {
+    size_t budget_bytes;    /* device memory the server may hold for resident requests      */
+    int32_t max_active;     /* requests executing at once (each on its own stream; 8)        */
+    int32_t precision;      /* default precision of submitted requests                      */
+} fdm_server_options;
+
+/* Creates a server on the current device.  Returns NULL on failure
+ * (fdm_last_error() says why). */
+fdm_server *fdm_server_create(const fdm_server_options *opt);
+
+/* Queues a request.  Hp is copied at submission (host memory if hp_on_host,
+ * else device memory) into a server-owned buffer; the caller may reuse it at
+ * once.  Returns FDM_ENOMEM if the request alone exceeds the budget,
+ * FDM_EINVAL for bad arguments.  *ticket identifies the request. */
+int fdm_submit(fdm_server *s, const double *Hp, int32_t hp_on_host, int64_t N, double n_occ,
+               double kT, double tol, int32_t precision, uint64_t *ticket);
+
+/* 0 = finished (result ready), 1 = pending, negative = unknown ticket. */
+int fdm_poll(fdm_server *s, uint64_t ticket);
+
+/* Blocks until the request finishes, copies D to D_out (host memory if
+ * out_on_host, else device; leading dimension ldd) and releases it.
+ * Returns the request's solve status.  times (host double[4], nullable):
+ * submit, start, finish and result times in seconds on the server clock. */
+int fdm_result(fdm_server *s, uint64_t ticket, double *D_out, int32_t out_on_host,
+               int64_t ldd, double *E_band, fdm_stats *stats, double *times);
+
+/* Waits for all requests, frees every resource. */
+void fdm_server_destroy(fdm_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FERMIDM_H */

@@ -1,0 +1,111 @@
+// Internal declarations shared by the kernels, the solver driver and the
+// server.  Everything here is gfx950 (CDNA4) specific.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "fermidm.h"
+
+namespace fdm {
+
+enum Prec : int { P_F64 = 0, P_F32 = 1, P_F16X3 = 2, P_BF16X3 = 3, P_BF16 = 4, P_F16 = 5 };
+
+// Working matrices are padded to a multiple of this edge; the padding holds
+// exact zeros at all times (every kernel writes zeros there and reads only
+// inside [0, N)^2 or inside zero padding), so product kernels need no bounds
+// checks.
+constexpr int kPadEdge = 128;
+// K is swept in stages of this many elements (all precisions divide it).
+constexpr int kKStep = 32;
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Decide-kernel modes (what the partial sums of the preceding launch mean).
+enum DecideMode : int {
+    D_INIT = 0,     // partials: Tr X, ||X||^2 of a new iterate; resets the phase
+    D_SP2 = 1,      // partials of an SP2 product: Tr X+, ||X+||^2, ||X^2 - X||^2
+    D_MCW_T = 2,    // partials of T = X X with E = X: ||X^2 - X||^2 in slot 2
+    D_MCW_OUT = 3,  // partials of X' = 3T - 2TX
+    D_SUMS = 4,     // plain reduction of (slot0, slot1, slot2) into st->sums
+};
+
+// Device-resident solver state: every branch and stop decision is taken on
+// the GPU from FP64 sums, so the host never has to read a scalar to enqueue
+// the next step.
+struct DevState {
+    double emin, emax, trH, fro2H;   // Gershgorin bounds and moments of Hp
+    double n_occ, tol, tau;
+    double trace, fro2;              // of the current iterate
+    double idem;                     // last measured ||X_n^2 - X_n||_F
+    double idem_hist[2];             // the two before it
+    double sums[4];                  // D_SUMS result
+    int32_t nonfinite;
+    int32_t sigma;                   // branch of the next SP2 product (1 = X^2)
+    int32_t done;                    // the current phase is finished
+    int32_t iter;                    // products that advanced the phase
+    int32_t result_iter;             // index of the result iterate when done
+    int32_t executed;                // product launches that ran in this phase
+    int32_t max_iter;
+    int32_t status;                  // 0 or a negative FDM_ status
+    int32_t switch_mode;             // 1: low-precision phase (stop on tau / stagnation)
+    int32_t gprod;                   // global SP2 product counter (branch bits)
+    uint64_t bits[4];
+};
+
+// What the host polls: written by the decide kernel into mapped pinned memory.
+struct HostMirror {
+    int32_t done, iter, result_iter, executed, status, sigma;
+    double idem, trace;
+};
+
+struct ProdArgs {
+    const void *A, *B, *E;
+    void *C;
+    int64_t ld;             // elements
+    int32_t n;              // logical size
+    int32_t kext;           // K extent (multiple of kKStep)
+    const uint32_t *tiles;  // (ti << 16) | tj, ti <= tj
+    int32_t ntiles;
+    int32_t pad;
+    double coef[2][3];      // {alpha, beta, gamma}, selected by *sel (0 if sel null)
+    const int32_t *sel;
+    const int32_t *done;    // nullable: exit at once if *done != 0
+    double *partials;       // [ntiles][4]
+};
+
+// ---- launchers (k_symprod.hip, k_aux.hip) --------------------------------
+hipError_t launch_symprod(int prec, int bt, const ProdArgs &a, hipStream_t s);
+
+// out = a * in + b * I on [0,n)^2, zeros on [0,np)^2 outside; in may be a
+// double (caller layout) or a float/double working matrix.  When zt_init is
+// set, (a, b) come from the Gershgorin bounds in st: a = -1/(emax-emin),
+// b = emax/(emax-emin).  Writes per-block (Tr, ||.||^2) partials.
+hipError_t launch_affine(int in_f32, const void *in, int64_t ldi, int out_f32, void *out,
+                         int64_t ldo, int n, int np, double a, double b, int zt_init,
+                         const DevState *st, double *partials, int *nparts, hipStream_t s);
+int affine_blocks(int np);
+
+hipError_t launch_gershgorin(const double *H, int64_t ldh, int n, double *partials,
+                             DevState *st, hipStream_t s);
+int gershgorin_blocks(int n);
+
+hipError_t launch_decide(DevState *st, HostMirror *hm, const double *partials, int count,
+                         int mode, int stride, hipStream_t s);
+
+hipError_t launch_energy(const double *H, int64_t ldh, const double *D, int64_t ldd,
+                         int d_f32, int n, double *partials, DevState *st, hipStream_t s);
+int energy_blocks(int n);
+
+hipError_t launch_copy_out(int src_f32, const void *src, int64_t lds, double *dst,
+                           int64_t ldd, int n, hipStream_t s);
+
+hipError_t launch_set_params(DevState *st, double n_occ, double tol, double tau, int max_iter,
+                             int switch_mode, int reset_all, hipStream_t s);
+
+// ---- errors ---------------------------------------------------------------
+void set_error(const std::string &msg);
+
+}  // namespace fdm

@@ -1,0 +1,322 @@
+// Finite temperature: the Fermi operator [exp(beta(H - mu I)) + I]^-1
+// (Sec. II.A) by a recursion of projection maps (Sec. II.B.3, Eq. (2)).
+//
+// With y = 1/2 - x the projection x -> x^2 / (x^2 + (1-x)^2) becomes the
+// doubling map y -> 2y / (1 + 4y^2), i.e. (1/2) tanh(a) -> (1/2) tanh(2a).
+// Starting from Y_0 = beta (H - mu I) / 2^(m+2) and applying it m times,
+//     D = I/2 - Y_m  ->  the Fermi operator as m grows
+// (closed form f_m(e) = 1/2 - 1/2 tanh(2^m atanh(beta (e - mu) / 2^(m+1))),
+// error O(4^-m)).  Each step is three kinds of symmetric products of
+// commuting matrices:
+//     S = Y^2,   Z ~ (I + 4S)^-1 by Newton-Schulz,   Y <- 2 Y Z.
+// The Newton-Schulz start Z_0 = 2/(2 + r) I uses the closed-form bound
+// r >= ||4 Y_k^2|| = tanh^2(2^k atanh(2 ||Y_0||)), so ||I - (I+4S) Z_0|| <=
+// r/(2+r) <= 1/3, and the number of iterations that reaches the working
+// precision is known on the host in advance; the first iteration is
+// elementwise (Z_1 = 2cI - c^2 (I + 4S)).  No scalar is read back inside an
+// evaluation.
+//
+// mu is unknown to the method: a safeguarded Newton iteration on
+// Tr D(mu) = n_occ (dTr/dmu = beta Tr(D - D^2), and Tr D^2 = ||D||_F^2),
+// optionally in low precision, then one FP64 evaluation at the final mu and
+// the first-order canonical correction D <- D + dmu beta (D - D^2).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "fdm_internal.h"
+#include "solver_internal.h"
+
+namespace fdm {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum2(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// sum (H_ij - H_ji)^2 and sum H_ij^2 over the caller's matrix
+__global__ __launch_bounds__(256) void k_symdiff(const double *__restrict__ H, int64_t ldh, int n,
+                                                 double *__restrict__ part) {
+    __shared__ double red[2][4];
+    double d2 = 0.0, h2 = 0.0;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        const int row = blockIdx.x * 4 + rr;
+        if (row >= n) break;
+        for (int c = threadIdx.x; c < n; c += 256) {
+            const double a = H[(int64_t)row * ldh + c], b = H[(int64_t)c * ldh + row];
+            d2 += (a - b) * (a - b);
+            h2 += a * a;
+        }
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    d2 = wave_sum2(d2);
+    h2 = wave_sum2(h2);
+    if (lane == 0) {
+        red[0][w] = d2;
+        red[1][w] = h2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double *p = part + (size_t)blockIdx.x * 4;
+        p[0] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+        p[1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        p[2] = 0.0;
+        p[3] = 0.0;
+    }
+}
+
+// Newton-Schulz iterations after the elementwise first one so that the
+// error bound e0^(2^J) reaches `target` (J counts all iterations).
+int ns_iterations(double r, double target) {
+    const double e0 = r / (2.0 + r);
+    if (e0 <= 0.0) return 0;
+    int J = 1;
+    double e = e0 * e0;
+    while (e > target && J < 12) {
+        e = e * e;
+        ++J;
+    }
+    return J - 1;
+}
+
+double ns_target(int prec) {
+    switch (prec) {
+        case P_F64: return 1e-17;
+        case P_F32:
+        case P_F16X3: return 1e-9;
+        case P_BF16X3: return 1e-6;
+        default: return 1e-4;
+    }
+}
+
+}  // namespace
+
+int fd_depth(double beta, double emin, double emax, double mu, int extra) {
+    const double r = beta * std::max(std::max(emax - mu, mu - emin), 1e-300);
+    return std::max(1, (int)ceil(log2(r)) + extra);
+}
+
+int Ctx::validate_symmetric(const double *Hp, int64_t ldh) {
+    const int nb = (int)((n + 3) / 4);
+    hipLaunchKernelGGL(k_symdiff, dim3(nb), dim3(256), 0, s, Hp, ldh, (int)n, r->part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "symmetry check launch");
+    int rc = decide(D_SUMS, nb, 4);
+    if (rc) return rc;
+    DevState h;
+    rc = read_state(&h);
+    if (rc) return rc;
+    if (!(sqrt(h.sums[0]) <= 1e-12 * sqrt(h.sums[1]))) {
+        set_error("Hp is not symmetric (||Hp - Hp^T||_F > 1e-12 ||Hp||_F)");
+        return FDM_EINVAL;
+    }
+    return FDM_OK;
+}
+
+// One evaluation of D(mu) by the doubling recursion in `prec` (FP64 or an
+// FP32-master low precision).  *result receives the working matrix holding
+// D; trace / trace_dd receive Tr D and Tr(D - D^2) (FP64 sums).
+int Ctx::fermi_operator(const double *Hp, int64_t ldh, double mu, int depth, int prec,
+                        void **result, int *result_f32, double *trace, double *trace_dd) {
+    const bool lo = prec != P_F64;
+    const size_t m = (size_t)r->lay.np * r->lay.ld;
+    void *buf[5];
+    for (int i = 0; i < 5; ++i)
+        buf[i] = lo ? (void *)(r->x32 + i * m) : (void *)(r->x64 + i * m);
+    const double beta = 1.0 / kT;
+    const double c0 = ldexp(beta, -(depth + 2));
+    // Y_0 = c0 (H - mu I)
+    int rc = affine(0, Hp, ldh, lo ? 1 : 0, buf[0], c0, -c0 * mu, 0, nullptr);
+    if (rc) return rc;
+    void *Y = buf[0], *S = buf[1], *Z = buf[2], *Z2 = buf[3], *W = buf[4];
+    // closed-form bound of ||Y_k||: (1/2) tanh(2^k atanh(2 ||Y_0||))
+    const double y0 = c0 * std::max(stats.e_max - mu, mu - stats.e_min);
+    const double a0 = atanh(std::min(2.0 * y0, 1.0 - 1e-16));
+    static const double c_sq[3] = {1.0, 0.0, 0.0};
+    static const double c_w[3] = {4.0, 1.0, 0.0};    // W = Z + 4 S Z
+    static const double c_z[3] = {-1.0, 2.0, 0.0};   // Z <- 2Z - Z W
+    static const double c_y[3] = {2.0, 0.0, 0.0};    // Y <- 2 Y Z
+    const double target = ns_target(prec);
+    for (int k = 0; k < depth; ++k) {
+        const double t = tanh(ldexp(a0, k));
+        const double rk = std::min(t * t, 1.0);
+        rc = product(prec, Y, Y, nullptr, S, c_sq, nullptr, false, false);
+        if (rc) return rc;
+        const double c = 2.0 / (2.0 + rk);
+        rc = affine(lo ? 1 : 0, S, r->lay.ld, lo ? 1 : 0, Z, -4.0 * c * c, 2.0 * c - c * c, 0,
+                    nullptr);
+        if (rc) return rc;
+        const int J = ns_iterations(rk, target);
+        for (int j = 0; j < J; ++j) {
+            rc = product(prec, S, Z, Z, W, c_w, nullptr, false, false);
+            if (rc) return rc;
+            rc = product(prec, Z, W, Z, Z2, c_z, nullptr, false, false);
+            if (rc) return rc;
+            std::swap(Z, Z2);
+        }
+        rc = product(prec, Y, Z, nullptr, S, c_y, nullptr, false, false);
+        if (rc) return rc;
+        std::swap(Y, S);
+    }
+    // D = I/2 - Y_m, with Tr D and ||D||_F^2
+    int np = 0;
+    rc = affine(lo ? 1 : 0, Y, r->lay.ld, lo ? 1 : 0, S, -1.0, 0.5, 0, &np);
+    if (rc) return rc;
+    rc = decide(D_SUMS, np, 4);
+    if (rc) return rc;
+    // every product of this evaluation ran (no device-side early exit)
+    close_phase((int)phase_launches.size());
+    DevState h;
+    rc = read_state(&h);
+    if (rc) return rc;
+    *result = S;
+    *result_f32 = lo ? 1 : 0;
+    *trace = h.sums[0];
+    *trace_dd = h.sums[0] - h.sums[1];
+    return FDM_OK;
+}
+
+int Ctx::solve_finite_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, double *E_band) {
+    DevState h;
+    int rc = bounds(Hp, ldh, &h);
+    if (rc) return rc;
+    const double beta = 1.0 / kT;
+    const int extra = opt.fd_extra_depth;
+    const int pe = opt.precision;  // precision of the mu search
+    // start: uniform-density-of-states guess from the exact moments
+    const double m1 = h.trH / (double)n;
+    const double m2 = std::max(h.fro2H / (double)n - m1 * m1, 0.0);
+    double mu = m1 + sqrt(3.0 * m2) * (2.0 * n_occ / (double)n - 1.0);
+    double lo_b = h.emin, hi_b = h.emax;
+    if (!(hi_b > lo_b)) {
+        lo_b -= 1.0;
+        hi_b += 1.0;
+    }
+    mu = std::min(std::max(mu, lo_b), hi_b);
+    void *dm = nullptr;
+    int dm_f32 = 0;
+    double tr = 0.0, trdd = 0.0;
+    int evals = 0, depth = 0;
+    const int max_evals = std::max(1, opt.max_mu_evals);
+    bool converged = false;
+    for (; evals < max_evals;) {
+        depth = fd_depth(beta, h.emin, h.emax, mu, extra);
+        rc = fermi_operator(Hp, ldh, mu, depth, pe, &dm, &dm_f32, &tr, &trdd);
+        if (rc) return rc;
+        ++evals;
+        const double err = tr - n_occ;
+        if (fabs(err) <= tol) {
+            converged = true;
+            break;
+        }
+        if (err < 0.0)
+            lo_b = mu;
+        else
+            hi_b = mu;
+        double step = (trdd > 1e-300) ? -err / (beta * trdd) : 0.0;
+        double next = mu + step;
+        if (!(next > lo_b && next < hi_b) || step == 0.0) next = 0.5 * (lo_b + hi_b);
+        if (pe != P_F64 && fabs(next - mu) <= 1e-7) {  // below the low-precision trace noise
+            mu = next;
+            converged = true;
+            break;
+        }
+        mu = next;
+    }
+    if (pe != P_F64) {
+        if (!opt.fd_final_fp64) {
+            // low precision end to end (reported, not gated): promote D
+            const size_t m = (size_t)r->lay.np * r->lay.ld;
+            int np = 0;
+            rc = affine(1, dm, r->lay.ld, 0, r->x64, 1.0, 0.0, 0, &np);
+            if (rc) return rc;
+            (void)m;
+            dm = r->x64;
+            dm_f32 = 0;
+        } else {
+            depth = fd_depth(beta, h.emin, h.emax, mu, extra);
+            rc = fermi_operator(Hp, ldh, mu, depth, P_F64, &dm, &dm_f32, &tr, &trdd);
+            if (rc) return rc;
+            ++evals;
+        }
+    }
+    stats.mu_evals = evals;
+    stats.depth = depth;
+    // first-order canonical correction: D <- (1 + c) D - c D^2,
+    // c = beta dmu, dmu = (n_occ - Tr D) / (beta Tr(D - D^2))
+    if (trdd > 1e-300) {
+        const double dmu = (n_occ - tr) / (beta * trdd);
+        const double c = beta * dmu;
+        const size_t m = (size_t)r->lay.np * r->lay.ld;
+        double *out = nullptr;
+        for (int i = 0; i < 5; ++i)
+            if ((void *)(r->x64 + i * m) != dm) {
+                out = r->x64 + i * m;
+                break;
+            }
+        const double coef[3] = {-c, 1.0 + c, 0.0};
+        rc = product(P_F64, dm, dm, dm, out, coef, nullptr, false, false);
+        if (rc) return rc;
+        close_phase(1);
+        dm = out;
+        mu += dmu;
+    }
+    stats.mu = mu;
+    if (!converged && pe == P_F64) status = FDM_ENOCONV;
+    return finish(Hp, ldh, dm, dm_f32, D, ldd, E_band);
+}
+
+}  // namespace fdm
+
+using namespace fdm;
+
+extern "C" int fdm_fermi_operator(const double *Hp, int64_t N, int64_t ldh, double mu, double kT,
+                                  int32_t depth, int32_t precision, double *D, int64_t ldd,
+                                  double *out, void *stream) {
+    set_error("");
+    if (!Hp || !D || N <= 0 || ldh < N || ldd < N || !(kT > 0.0) || precision < 0 ||
+        precision >= FDM_NPREC || !std::isfinite(mu))
+        return FDM_EINVAL;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    Resources *r = thread_resources(dev);
+    if (!r) return FDM_EHIP;
+    Ctx c;
+    c.r = r;
+    c.s = (hipStream_t)stream;
+    fdm_options_default(&c.opt);
+    memset(&c.stats, 0, sizeof(c.stats));
+    c.n = N;
+    c.kT = kT;
+    int rc = r->bind(plan_layout(N, true, precision), nullptr, 0, c.s);
+    if (rc) return rc;
+    DevState h;
+    rc = c.bounds(Hp, ldh, &h);
+    if (rc) return rc;
+    if (depth <= 0) depth = fd_depth(1.0 / kT, h.emin, h.emax, mu, c.opt.fd_extra_depth);
+    if (ldexp(1.0, depth + 1) <= (1.0 / kT) * std::max(h.emax - mu, mu - h.emin)) {
+        set_error("depth too small for the spectral range: 2^(depth+1) must exceed beta*R");
+        return FDM_EINVAL;
+    }
+    void *dm = nullptr;
+    int f32 = 0;
+    double tr = 0.0, trdd = 0.0;
+    rc = c.fermi_operator(Hp, ldh, mu, depth, precision, &dm, &f32, &tr, &trdd);
+    if (rc) return rc;
+    e = launch_copy_out(f32, dm, r->lay.ld, D, ldd, (int)N, c.s);
+    if (e != hipSuccess) return hip_fail(e, "copy-out launch");
+    e = hipStreamSynchronize(c.s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (out) {
+        out[0] = tr;
+        out[1] = trdd;
+        out[2] = (double)depth;
+    }
+    return FDM_OK;
+}

@@ -1,0 +1,363 @@
+// Symmetric-product kernel of the recursive Fermi-operator expansion.
+//
+// The hot loop of every recursion in the paper (Sec. II.B, Eq. (1) and
+// Eq. (2)) multiplies two commuting symmetric matrices, so the product is
+// symmetric and only its upper-triangular tiles are computed (N^2 (N+1)
+// flops instead of 2 N^3); each off-diagonal tile is stored twice (mirror).
+// The epilogue fuses the projection step, C = alpha*AB + beta*E + gamma*I
+// with (alpha, beta, gamma) chosen on the device from the SP2 branch flag
+// (X^2 or 2X - X^2), and the FP64 partial sums the next decision needs:
+// Tr C, ||C||_F^2 (= Tr C^2 for symmetric C, Sec. III.B) and ||AB - E||_F^2
+// (the idempotency error of X when AB = X^2 and E = X).
+//
+// CDNA4 mapping:
+//  * 256 threads = 4 wave64s in a 2 x 2 arrangement; a block owns a BT x BT
+//    output tile, each wave a (BT/2)^2 sub-tile of 16 x 16 MFMA blocks.
+//  * Both operands are read as row panels of the row-major matrices: rows
+//    ti*BT.. of A and rows tj*BT.. of B (B symmetric, so B[k][j] = B[j][k]),
+//    16-byte global loads along k, staged through LDS rows padded by 16 bytes
+//    (conflict-free 16-byte fragment reads), double buffered with one barrier
+//    per stage and the next stage's global loads issued before the MFMAs.
+//  * Every lane reads a 16-byte fragment (row = lane % 16, k-chunk =
+//    lane / 16).  The k order inside a fragment is irrelevant because A and
+//    B use the same one: FP64 feeds 2 v_mfma_f64_16x16x4 per fragment, FP32
+//    4 v_mfma_f32_16x16x4, FP16/BF16 one v_mfma_f32_16x16x32.
+//  * Split forms keep an FP32 master matrix and split it while staging:
+//    hi = round(s*x), lo = round(s*x - hi) (s = 2^12 for FP16, 1 for BF16),
+//    AB ~ (hi hi + hi lo + lo hi) / s^2 with FP32 accumulation.
+//  * Workgroups go round-robin over the 8 XCDs; the block index is remapped
+//    so each XCD works on a contiguous run of the tile list (shared row
+//    panels stay in that XCD's L2).
+//  * Working matrices are zero-padded to a multiple of 128, so no bounds
+//    checks are needed; partial sums are per tile and reduced in a fixed
+//    order by the decide kernel (bitwise reproducible).
+#include "fdm_internal.h"
+
+namespace fdm {
+namespace {
+
+typedef double d2_t __attribute__((ext_vector_type(2)));
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 b4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 b8_t __attribute__((ext_vector_type(8)));
+typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u2_t __attribute__((ext_vector_type(2)));
+
+template <class To, class From>
+__device__ __forceinline__ To bitcast(const From &v) {
+    static_assert(sizeof(To) == sizeof(From), "size");
+    return __builtin_bit_cast(To, v);
+}
+
+template <int P>
+struct PT;
+template <>
+struct PT<P_F64> {
+    using S = double;
+    using Acc = d4_t;
+    static constexpr bool HALF = false, SPLIT = false, F16 = false;
+};
+template <>
+struct PT<P_F32> {
+    using S = float;
+    using Acc = f4_t;
+    static constexpr bool HALF = false, SPLIT = false, F16 = false;
+};
+template <>
+struct PT<P_F16X3> {
+    using S = float;
+    using Acc = f4_t;
+    static constexpr bool HALF = true, SPLIT = true, F16 = true;
+};
+template <>
+struct PT<P_BF16X3> {
+    using S = float;
+    using Acc = f4_t;
+    static constexpr bool HALF = true, SPLIT = true, F16 = false;
+};
+template <>
+struct PT<P_F16> {
+    using S = float;
+    using Acc = f4_t;
+    static constexpr bool HALF = true, SPLIT = false, F16 = true;
+};
+template <>
+struct PT<P_BF16> {
+    using S = float;
+    using Acc = f4_t;
+    static constexpr bool HALF = true, SPLIT = false, F16 = false;
+};
+
+// FP16 forms work on 2^12 * x so that small entries stay normal.
+constexpr float kF16Scale = 4096.0f;
+constexpr double kF16Unscale = 1.0 / (4096.0 * 4096.0);
+
+// Split (or round) four FP32 values into 16-bit halves.
+template <int P>
+__device__ __forceinline__ void to_halves(const u4_t &raw, u2_t &hi, u2_t &lo) {
+    const f4_t x = bitcast<f4_t>(raw);
+    if constexpr (PT<P>::F16) {
+        h4_t h, l;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float s = x[e] * kF16Scale;
+            const _Float16 hh = (_Float16)s;
+            h[e] = hh;
+            l[e] = (_Float16)(s - (float)hh);
+        }
+        hi = bitcast<u2_t>(h);
+        lo = bitcast<u2_t>(l);
+    } else {
+        b4_t h, l;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const __bf16 hh = (__bf16)x[e];
+            h[e] = hh;
+            l[e] = (__bf16)(x[e] - (float)hh);
+        }
+        hi = bitcast<u2_t>(h);
+        lo = bitcast<u2_t>(l);
+    }
+}
+
+template <int P>
+__device__ __forceinline__ typename PT<P>::Acc mfma_frag(const u4_t &a, const u4_t &b,
+                                                         const u4_t &alo, const u4_t &blo,
+                                                         typename PT<P>::Acc c) {
+    if constexpr (P == P_F64) {
+        const d2_t x = bitcast<d2_t>(a), y = bitcast<d2_t>(b);
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(x[0], y[0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(x[1], y[1], c, 0, 0, 0);
+    } else if constexpr (P == P_F32) {
+        const f4_t x = bitcast<f4_t>(a), y = bitcast<f4_t>(b);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[0], y[0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[1], y[1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[2], y[2], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[3], y[3], c, 0, 0, 0);
+    } else if constexpr (PT<P>::F16) {
+        const h8_t x = bitcast<h8_t>(a), y = bitcast<h8_t>(b);
+        if constexpr (PT<P>::SPLIT) {
+            const h8_t xl = bitcast<h8_t>(alo), yl = bitcast<h8_t>(blo);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_f16(x, yl, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_f16(xl, y, c, 0, 0, 0);
+        }
+        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, c, 0, 0, 0);
+    } else {
+        const b8_t x = bitcast<b8_t>(a), y = bitcast<b8_t>(b);
+        if constexpr (PT<P>::SPLIT) {
+            const b8_t xl = bitcast<b8_t>(alo), yl = bitcast<b8_t>(blo);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, yl, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, y, c, 0, 0, 0);
+        }
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
+    }
+    return c;
+}
+
+template <int P, int BT>
+__global__ __launch_bounds__(256) void k_symprod(ProdArgs a) {
+    if (a.done != nullptr && *a.done) return;
+    using T = PT<P>;
+    using S = typename T::S;
+    using Acc = typename T::Acc;
+    constexpr bool HALF = T::HALF;
+    constexpr bool SPLIT = T::SPLIT;
+    constexpr int RSB = HALF ? 80 : 144;           // LDS row stride (bytes): 64|128 + 16 pad
+    constexpr int NARR = SPLIT ? 2 : 1;            // hi (+ lo) arrays per operand
+    constexpr int PANEL = BT * RSB;                // bytes of one operand array
+    constexpr int KST = (sizeof(S) == 8) ? 16 : 32;  // k elements per stage (128 B of S)
+    constexpr int EPC = 16 / sizeof(S);            // S elements per 16-byte chunk
+    constexpr int GROUPS = HALF ? 1 : 2;           // 64-byte fragment groups per stage
+    constexpr int NL = BT * 8 / 256;               // 16-byte global chunks per thread per panel
+    constexpr int WT = BT / 2;
+    constexpr int FM = WT / 16;
+
+    __shared__ __attribute__((aligned(16))) unsigned char lds[2 * 2 * NARR * PANEL];
+
+    const int tid = threadIdx.x;
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int xcd = b & 7, slot = b >> 3, per = nb >> 3, rem = nb & 7;
+    const int t = (xcd < rem) ? xcd * (per + 1) + slot
+                              : rem * (per + 1) + (xcd - rem) * per + slot;
+    const uint32_t tt = a.tiles[t];
+    const int ti = (int)(tt >> 16), tj = (int)(tt & 0xffffu);
+    const int64_t row0 = (int64_t)ti * BT, col0 = (int64_t)tj * BT;
+    const int64_t ld = a.ld;
+    const S *__restrict__ A = (const S *)a.A;
+    const S *__restrict__ B = (const S *)a.B;
+
+    u4_t ga[NL], gb[NL];
+    auto gload = [&](int kt) {
+        const int64_t k0 = (int64_t)kt * KST;
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int c = tid + 256 * u;
+            const int r = c >> 3, ch = c & 7;
+            ga[u] = *(const u4_t *)(A + (row0 + r) * ld + k0 + ch * EPC);
+            gb[u] = *(const u4_t *)(B + (col0 + r) * ld + k0 + ch * EPC);
+        }
+    };
+    auto lstore = [&](int st) {
+        unsigned char *pa = lds + (st * 2 + 0) * NARR * PANEL;
+        unsigned char *pb = lds + (st * 2 + 1) * NARR * PANEL;
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int c = tid + 256 * u;
+            const int r = c >> 3, ch = c & 7;
+            if constexpr (!HALF) {
+                *(u4_t *)(pa + r * RSB + ch * 16) = ga[u];
+                *(u4_t *)(pb + r * RSB + ch * 16) = gb[u];
+            } else {
+                u2_t h, l;
+                to_halves<P>(ga[u], h, l);
+                *(u2_t *)(pa + r * RSB + ch * 8) = h;
+                if constexpr (SPLIT) *(u2_t *)(pa + PANEL + r * RSB + ch * 8) = l;
+                to_halves<P>(gb[u], h, l);
+                *(u2_t *)(pb + r * RSB + ch * 8) = h;
+                if constexpr (SPLIT) *(u2_t *)(pb + PANEL + r * RSB + ch * 8) = l;
+            }
+        }
+    };
+
+    const int w = tid >> 6, lane = tid & 63;
+    const int wr = w >> 1, wc = w & 1, lr = lane & 15, lg = lane >> 4;
+    Acc acc[FM][FM];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FM; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+
+    auto compute = [&](int st) {
+        const unsigned char *pa = lds + (st * 2 + 0) * NARR * PANEL;
+        const unsigned char *pb = lds + (st * 2 + 1) * NARR * PANEL;
+#pragma unroll
+        for (int g = 0; g < GROUPS; ++g) {
+            u4_t fa[FM], fb[FM], fal[FM], fbl[FM];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                const int off = (wr * WT + i * 16 + lr) * RSB + (g * 4 + lg) * 16;
+                fa[i] = *(const u4_t *)(pa + off);
+                if constexpr (SPLIT) fal[i] = *(const u4_t *)(pa + PANEL + off);
+            }
+#pragma unroll
+            for (int j = 0; j < FM; ++j) {
+                const int off = (wc * WT + j * 16 + lr) * RSB + (g * 4 + lg) * 16;
+                fb[j] = *(const u4_t *)(pb + off);
+                if constexpr (SPLIT) fbl[j] = *(const u4_t *)(pb + PANEL + off);
+            }
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FM; ++j)
+                    acc[i][j] = mfma_frag<P>(fa[i], fb[j], fal[i], fbl[j], acc[i][j]);
+        }
+    };
+
+    const int nk = a.kext / KST;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload(kt + 1);
+        compute(cur);
+        if (kt + 1 < nk) lstore(cur ^ 1);
+        __syncthreads();
+    }
+
+    // ---- fused epilogue -------------------------------------------------
+    const int sel = (a.sel != nullptr) ? *a.sel : 0;
+    const double alpha = a.coef[sel][0], beta = a.coef[sel][1], gamma = a.coef[sel][2];
+    const double scale = (HALF && T::F16) ? kF16Unscale : 1.0;
+    const S *__restrict__ E = (const S *)a.E;
+    S *__restrict__ C = (S *)a.C;
+    const bool diag = (ti == tj);
+    double s_tr = 0.0, s_f2 = 0.0, s_d2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+        for (int j = 0; j < FM; ++j) {
+            const int64_t rbase = row0 + wr * WT + i * 16 + 4 * lg;
+            const int64_t col = col0 + wc * WT + j * 16 + lr;
+            S ov[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t row = rbase + q;
+                const double v = (double)acc[i][j][q] * scale;
+                const double e = (E != nullptr) ? (double)E[row * ld + col] : 0.0;
+                double o = alpha * v + beta * e;
+                if (row == col && row < a.n) o += gamma;
+                const S os = (S)o;
+                ov[q] = os;
+                C[row * ld + col] = os;
+                const double od = (double)os;
+                if (row == col) s_tr += od;
+                s_f2 += od * od;
+                s_d2 += (v - e) * (v - e);
+            }
+            if (!diag) {
+                S *dst = C + col * ld + rbase;
+                if constexpr (sizeof(S) == 8) {
+                    *(d4_t *)dst = d4_t{(double)ov[0], (double)ov[1], (double)ov[2], (double)ov[3]};
+                } else {
+                    *(f4_t *)dst = f4_t{(float)ov[0], (float)ov[1], (float)ov[2], (float)ov[3]};
+                }
+            }
+        }
+    }
+    const double wgt = diag ? 1.0 : 2.0;
+    s_f2 *= wgt;
+    s_d2 *= wgt;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        s_tr += __shfl_xor(s_tr, off);
+        s_f2 += __shfl_xor(s_f2, off);
+        s_d2 += __shfl_xor(s_d2, off);
+    }
+    double *red = (double *)lds;  // every wave is past the last barrier of the k loop
+    if (lane == 0) {
+        red[w * 3 + 0] = s_tr;
+        red[w * 3 + 1] = s_f2;
+        red[w * 3 + 2] = s_d2;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double *p = a.partials + (size_t)t * 4;
+        p[0] = (red[0] + red[3]) + (red[6] + red[9]);
+        p[1] = (red[1] + red[4]) + (red[7] + red[10]);
+        p[2] = (red[2] + red[5]) + (red[8] + red[11]);
+        p[3] = 0.0;
+    }
+}
+
+template <int P, int BT>
+hipError_t launch_t(const ProdArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_symprod<P, BT>), dim3(a.ntiles), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_p(int bt, const ProdArgs &a, hipStream_t s) {
+    if (bt == 128) return launch_t<P, 128>(a, s);
+    return launch_t<P, 64>(a, s);
+}
+
+}  // namespace
+
+hipError_t launch_symprod(int prec, int bt, const ProdArgs &a, hipStream_t s) {
+    if (a.ntiles <= 0) return hipSuccess;
+    switch (prec) {
+        case P_F64: return launch_p<P_F64>(bt, a, s);
+        case P_F32: return launch_p<P_F32>(bt, a, s);
+        case P_F16X3: return launch_p<P_F16X3>(bt, a, s);
+        case P_BF16X3: return launch_p<P_BF16X3>(bt, a, s);
+        case P_BF16: return launch_p<P_BF16>(bt, a, s);
+        case P_F16: return launch_p<P_F16>(bt, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace fdm

@@ -1,0 +1,765 @@
+// Solver driver and C ABI.
+//
+// Zero temperature (Sec. II.B.1, Eq. (1)):
+//   bounds (Gershgorin, Sec. II.C) -> X_0 = (e_max I - H)/(e_max - e_min) ->
+//   SP2 products, each fused with its branch update and trace sums, the
+//   branch for the next product and the stop test decided on the device.
+// Mixed precision (Sec. III.A): a few FP64 SP2 steps, then low-precision SP2
+//   steps on an FP32 master until ||X^2 - X||_F <= tau, then FP64 McWeeny
+//   steps X <- 3X^2 - 2X^3 until ||X^2 - X||_F <= tol.
+// Finite temperature (Sec. II.B.3, Eq. (2)): see finite_t.hip.
+//
+// The host enqueues one step ahead of what it has observed: it waits on the
+// event of step k-1 while step k runs, so the device never idles on a host
+// round trip, and at most one step per phase is launched after convergence
+// (those launches see the device "done" flag and return at once).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fdm_internal.h"
+#include "solver_internal.h"
+
+namespace fdm {
+
+static thread_local std::string tl_err;
+void set_error(const std::string &msg) { tl_err = msg; }
+const char *last_error() { return tl_err.c_str(); }
+
+int hip_fail(hipError_t e, const char *what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return FDM_EHIP;
+}
+
+// ---------------------------------------------------------------------------
+// tile lists
+// ---------------------------------------------------------------------------
+static std::vector<uint32_t> upper_tiles(int nt) {
+    std::vector<uint32_t> v;
+    v.reserve((size_t)nt * (nt + 1) / 2);
+    for (int i = 0; i < nt; ++i)
+        for (int j = i; j < nt; ++j) v.push_back(((uint32_t)i << 16) | (uint32_t)j);
+    return v;
+}
+
+static int64_t ntiles_for(int64_t n, int bt) {
+    const int64_t nt = (n + bt - 1) / bt;
+    return nt * (nt + 1) / 2;
+}
+
+// ---------------------------------------------------------------------------
+// workspace
+// ---------------------------------------------------------------------------
+Layout plan_layout(int64_t n, bool finite, int prec) {
+    Layout L;
+    L.n = n;
+    L.np = round_up(std::max<int64_t>(n, 1), kPadEdge);
+    L.ld = L.np;
+    L.n64 = finite ? 5 : 3;
+    L.n32 = (prec == P_F64) ? 0 : (finite ? 5 : 2);
+    const size_t mat64 = (size_t)L.np * L.ld * 8, mat32 = (size_t)L.np * L.ld * 4;
+    const int64_t tiles64 = ntiles_for(n, 64), tiles128 = ntiles_for(n, 128);
+    const int64_t parts = std::max<int64_t>({tiles64, (L.np + 3) / 4, 1});
+    size_t off = 0;
+    L.off64 = off;
+    off += mat64 * L.n64;
+    L.off32 = off;
+    off += mat32 * L.n32;
+    L.off_part = off;
+    off += round_up(parts * 8 * sizeof(double), 256);
+    L.off_tiles64 = off;
+    off += round_up(tiles64 * 4, 256);
+    L.off_tiles128 = off;
+    off += round_up(tiles128 * 4, 256);
+    L.off_state = off;
+    off += round_up(sizeof(DevState), 256);
+    L.bytes = off;
+    L.ntiles64 = (int)tiles64;
+    L.ntiles128 = (int)tiles128;
+    L.part_cap = parts;
+    return L;
+}
+
+Resources::~Resources() {
+    for (hipEvent_t e : ev) hipEventDestroy(e);
+    for (hipEvent_t e : tev) hipEventDestroy(e);
+    if (owned && base) hipFree(base);
+    // the mapped host mirror is intentionally kept until process exit
+}
+
+int Resources::init(int dev) {
+    device = dev;
+    hipError_t e;
+    for (int i = 0; i < 2; ++i) {
+        e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+    e = hipHostMalloc((void **)&hm_host, sizeof(HostMirror),
+                      hipHostMallocMapped | hipHostMallocCoherent);
+    if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
+    memset((void *)hm_host, 0, sizeof(HostMirror));
+    e = hipHostGetDevicePointer((void **)&hm_dev, (void *)hm_host, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipHostGetDevicePointer");
+    return FDM_OK;
+}
+
+int Resources::bind(const Layout &L, void *user_mem, size_t user_bytes, hipStream_t s) {
+    hipError_t e;
+    char *mem;
+    if (user_mem) {
+        if (user_bytes < L.bytes) {
+            set_error("workspace_bytes smaller than fdm_workspace_bytes()");
+            return FDM_EINVAL;
+        }
+        mem = (char *)user_mem;
+    } else {
+        if (!owned || cap < L.bytes) {
+            if (owned && base) {
+                e = hipStreamSynchronize(s);
+                if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+                hipFree(base);
+            }
+            base = nullptr;
+            owned = false;
+            cap = 0;
+            e = hipMalloc((void **)&base, L.bytes);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                set_error("hipMalloc of " + std::to_string(L.bytes) + " workspace bytes failed");
+                return FDM_ENOMEM;
+            }
+            owned = true;
+            cap = L.bytes;
+            bound_key = -1;
+        }
+        mem = base;
+    }
+    // A caller-provided block may have been used by anyone since: always
+    // re-zero it and re-upload the tile lists.
+    const bool fresh = user_mem != nullptr || (mem != bound_mem) ||
+                       bound_key != (L.n * 16 + L.n64 * 4 + L.n32) || bound_ld != L.ld;
+    lay = L;
+    x64 = (double *)(mem + L.off64);
+    x32 = (float *)(mem + L.off32);
+    part = (double *)(mem + L.off_part);
+    tiles64 = (uint32_t *)(mem + L.off_tiles64);
+    tiles128 = (uint32_t *)(mem + L.off_tiles128);
+    st = (DevState *)(mem + L.off_state);
+    if (fresh) {
+        // zero every matrix (the padding must hold zeros) and upload tile lists
+        e = hipMemsetAsync(mem, 0, L.off_part, s);
+        if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+        e = hipMemsetAsync(st, 0, sizeof(DevState), s);
+        if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+        std::vector<uint32_t> t64 = upper_tiles((int)((L.n + 63) / 64));
+        std::vector<uint32_t> t128 = upper_tiles((int)((L.n + 127) / 128));
+        e = hipMemcpyAsync(tiles64, t64.data(), t64.size() * 4, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+        e = hipMemcpyAsync(tiles128, t128.data(), t128.size() * 4, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+        e = hipStreamSynchronize(s);  // the host vectors die here
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        bound_mem = mem;
+        bound_key = L.n * 16 + L.n64 * 4 + L.n32;
+        bound_ld = L.ld;
+    }
+    return FDM_OK;
+}
+
+hipEvent_t Resources::timing_event(size_t i) {
+    while (tev.size() <= i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        tev.push_back(e);
+    }
+    return tev[i];
+}
+
+static std::mutex g_res_mu;
+
+Resources *thread_resources(int dev) {
+    thread_local std::vector<std::unique_ptr<Resources>> pool;
+    if ((int)pool.size() <= dev) pool.resize(dev + 1);
+    if (!pool[dev]) {
+        std::unique_ptr<Resources> r(new Resources());
+        if (r->init(dev) != FDM_OK) return nullptr;
+        pool[dev] = std::move(r);
+    }
+    return pool[dev].get();
+}
+
+// ---------------------------------------------------------------------------
+// context helpers
+// ---------------------------------------------------------------------------
+int Ctx::tile_for(int prec) const {
+    if (opt.tile == 64 || opt.tile == 128) return opt.tile;
+    // FP64 / FP32: 64-wide tiles keep > 4 waves of work on 256 CUs up to
+    // N ~ 8k; larger problems amortise the panel loads with 128-wide tiles.
+    const int64_t t128 = ntiles_for(n, 128);
+    if (prec == P_F64 || prec == P_F32) return (t128 >= 4 * 256) ? 128 : 64;
+    return (t128 >= 2 * 256) ? 128 : 64;
+}
+
+int Ctx::product(int prec, const void *A, const void *B, const void *E, void *C,
+                 const double c0[3], const double c1[3], bool sel, bool done_guard) {
+    ProdArgs a;
+    memset(&a, 0, sizeof(a));
+    const int bt = tile_for(prec);
+    a.A = A;
+    a.B = B;
+    a.E = E;
+    a.C = C;
+    a.ld = r->lay.ld;
+    a.n = (int32_t)n;
+    a.kext = (int32_t)round_up(n, kKStep);
+    a.tiles = (bt == 128) ? r->tiles128 : r->tiles64;
+    a.ntiles = (bt == 128) ? r->lay.ntiles128 : r->lay.ntiles64;
+    for (int k = 0; k < 3; ++k) {
+        a.coef[0][k] = c0[k];
+        a.coef[1][k] = c1 ? c1[k] : c0[k];
+    }
+    a.sel = sel ? &r->st->sigma : nullptr;
+    a.done = done_guard ? &r->st->done : nullptr;
+    a.partials = r->part;
+    last_ntiles = a.ntiles;
+    used_tile = bt;
+    hipError_t e;
+    if (opt.timing) {
+        hipEvent_t e0 = r->timing_event(2 * timed.size()), e1 = r->timing_event(2 * timed.size() + 1);
+        if (!e0 || !e1) return hip_fail(hipErrorOutOfMemory, "hipEventCreate");
+        e = hipEventRecord(e0, s);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        e = launch_symprod(prec, bt, a, s);
+        if (e != hipSuccess) return hip_fail(e, "symmetric product launch");
+        e = hipEventRecord(e1, s);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        timed.push_back({prec, 2 * timed.size(), 2 * timed.size() + 1, true});
+    } else {
+        e = launch_symprod(prec, bt, a, s);
+        if (e != hipSuccess) return hip_fail(e, "symmetric product launch");
+    }
+    phase_launches.push_back(prec);
+    return FDM_OK;
+}
+
+// Product launches of the finished phase that did work: the first `executed`
+// of them.  The rest returned at once on the device's done flag.
+void Ctx::close_phase(int executed) {
+    const size_t keep = std::min<size_t>((size_t)std::max(executed, 0), phase_launches.size());
+    for (size_t i = 0; i < keep; ++i) {
+        const int p = phase_launches[i];
+        stats.products[p] += 1;
+        const double nn = (double)n;
+        stats.flops[p] += nn * nn * (nn + 1.0) * ((p == P_F16X3 || p == P_BF16X3) ? 3.0 : 1.0);
+    }
+    if (opt.timing) {
+        // timed entries of this phase are the last phase_launches.size() ones
+        const size_t first = timed.size() - phase_launches.size();
+        for (size_t i = first + keep; i < timed.size(); ++i) timed[i].real = false;
+    }
+    phase_launches.clear();
+}
+
+int Ctx::decide(int mode, int count, int stride) {
+    hipError_t e = launch_decide(r->st, r->hm_dev, r->part, count, mode, stride, s);
+    return e == hipSuccess ? FDM_OK : hip_fail(e, "decide launch");
+}
+
+int Ctx::set_params(double tau, int max_iter, int switch_mode, int reset_all) {
+    hipError_t e = launch_set_params(r->st, n_occ, tol, tau, max_iter, switch_mode, reset_all, s);
+    return e == hipSuccess ? FDM_OK : hip_fail(e, "set_params launch");
+}
+
+int Ctx::affine(int in_f32, const void *in, int64_t ldi, int out_f32, void *out, double a,
+                double b, int zt, int *nparts) {
+    hipError_t e = launch_affine(in_f32, in, ldi, out_f32, out, r->lay.ld, (int)n,
+                                 (int)r->lay.np, a, b, zt, r->st, r->part, nparts, s);
+    return e == hipSuccess ? FDM_OK : hip_fail(e, "affine launch");
+}
+
+// Runs `enqueue(k)` for k = 0, 1, ... keeping exactly one step in flight
+// beyond the last one observed, until the device reports done.
+int Ctx::run_loop(int max_steps, const std::function<int(int)> &enqueue) {
+    int rc = enqueue(0);
+    if (rc) return rc;
+    hipError_t e = hipEventRecord(r->ev[0], s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    for (int k = 1; k <= max_steps + 1; ++k) {
+        if (k < max_steps) {
+            rc = enqueue(k);
+            if (rc) return rc;
+            e = hipEventRecord(r->ev[k & 1], s);
+            if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        }
+        e = hipEventSynchronize(r->ev[(k - 1) & 1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        if (r->hm_host->done) return FDM_OK;
+        if (k >= max_steps) break;
+    }
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (r->hm_host->done) return FDM_OK;
+    set_error("internal: phase ended without a device decision");
+    return FDM_EHIP;
+}
+
+// SP2 products from X_0 in bufs[0] (its sums already reduced by D_INIT).
+int Ctx::sp2_phase(int prec, void *b0, void *b1, int max_iter, int switch_mode, double tau,
+                   void **result, int *iters) {
+    int rc = set_params(tau, max_iter, switch_mode, 0);
+    if (rc) return rc;
+    void *bufs[2] = {b0, b1};
+    // sel = 0: 2X - X^2 ;  sel = 1: X^2
+    static const double c_sub[3] = {-1.0, 2.0, 0.0};
+    static const double c_sq[3] = {1.0, 0.0, 0.0};
+    rc = run_loop(max_iter, [&](int k) -> int {
+        int q = product(prec, bufs[k & 1], bufs[k & 1], bufs[k & 1], bufs[(k + 1) & 1], c_sub,
+                        c_sq, true, true);
+        if (q) return q;
+        return decide(D_SP2, last_ntiles, 4);
+    });
+    if (rc) return rc;
+    const HostMirror hm = *r->hm_host;
+    close_phase(hm.executed);
+    *result = bufs[hm.result_iter & 1];
+    if (iters) *iters = hm.iter;
+    if (hm.status) status = hm.status;
+    return FDM_OK;
+}
+
+// FP64 McWeeny steps from X in x[0]: T = X X (measures ||X^2 - X||), then
+// X <- 3T - 2 T X.  Buffers x[0], x[2] alternate as X; x[1] holds T.
+int Ctx::mcweeny_phase(double *x0, double *t, double *x1, int max_steps, double **result,
+                       int *steps) {
+    int rc = set_params(0.0, max_steps, 0, 0);
+    if (rc) return rc;
+    double *xs[2] = {x0, x1};
+    static const double c_t[3] = {1.0, 0.0, 0.0};
+    static const double c_out[3] = {-2.0, 3.0, 0.0};
+    rc = run_loop(max_steps + 1, [&](int k) -> int {
+        double *x = xs[k & 1], *xn = xs[(k + 1) & 1];
+        int q = product(P_F64, x, x, x, t, c_t, nullptr, false, true);
+        if (q) return q;
+        q = decide(D_MCW_T, last_ntiles, 4);
+        if (q) return q;
+        q = product(P_F64, t, x, t, xn, c_out, nullptr, false, true);
+        if (q) return q;
+        return decide(D_MCW_OUT, last_ntiles, 4);
+    });
+    if (rc) return rc;
+    const HostMirror hm = *r->hm_host;
+    close_phase(hm.executed);
+    *result = xs[hm.result_iter & 1];
+    if (steps) *steps = hm.result_iter;
+    if (hm.status) status = hm.status;
+    stats.idempotency = hm.idem;
+    return FDM_OK;
+}
+
+int Ctx::read_state(DevState *out) {
+    hipError_t e = hipMemcpyAsync(r->st_host(), r->st, sizeof(DevState), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    *out = *r->st_host();
+    return FDM_OK;
+}
+
+DevState *Resources::st_host() {
+    if (!st_pinned) {
+        if (hipHostMalloc((void **)&st_pinned, sizeof(DevState), hipHostMallocDefault) != hipSuccess)
+            st_pinned = &st_fallback;
+    }
+    return st_pinned;
+}
+
+// Finishes a solve whose density matrix is the FP64 working matrix `dm`.
+int Ctx::finish(const double *Hp, int64_t ldh, const void *dm, int dm_f32, double *D, int64_t ldd,
+                double *E_band) {
+    hipError_t e = launch_energy(Hp, ldh, (const double *)dm, r->lay.ld, dm_f32, (int)n, r->part,
+                                 r->st, s);
+    if (e != hipSuccess) return hip_fail(e, "energy launch");
+    e = launch_copy_out(dm_f32, dm, r->lay.ld, D, ldd, (int)n, s);
+    if (e != hipSuccess) return hip_fail(e, "copy-out launch");
+    DevState h;
+    int rc = read_state(&h);
+    if (rc) return rc;
+    stats.band_energy = h.sums[0];
+    stats.trace = h.sums[1];
+    for (int k = 0; k < 4; ++k) stats.branch_bits[k] = h.bits[k];
+    if (E_band) *E_band = h.sums[0];
+    return FDM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// zero temperature
+// ---------------------------------------------------------------------------
+static double unit_roundoff(int prec) {
+    switch (prec) {
+        case P_F64: return 1.1e-16;
+        case P_F32: return 6.0e-8;
+        case P_F16X3: return 6.0e-8;
+        case P_BF16X3: return 1.5e-5;
+        case P_F16: return 4.9e-4;
+        default: return 3.9e-3;
+    }
+}
+
+int Ctx::bounds(const double *Hp, int64_t ldh, DevState *h) {
+    hipError_t e = launch_gershgorin(Hp, ldh, (int)n, r->part, r->st, s);
+    if (e != hipSuccess) return hip_fail(e, "gershgorin launch");
+    int rc = read_state(h);
+    if (rc) return rc;
+    stats.e_min = h->emin;
+    stats.e_max = h->emax;
+    if (h->nonfinite) {
+        set_error("Hp holds NaN or Inf in " + std::to_string(h->nonfinite) + " rows");
+        return FDM_ENONFINITE;
+    }
+    return FDM_OK;
+}
+
+int Ctx::solve_zero_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, double *E_band) {
+    const int64_t k = (int64_t)llround(n_occ);
+    DevState h;
+    int rc = bounds(Hp, ldh, &h);
+    if (rc) return rc;
+    if (k == 0 || k == n) {
+        // D = 0 or I exactly
+        hipError_t e = launch_affine(0, Hp, ldh, 0, D, ldd, (int)n, (int)n, 0.0,
+                                     k == 0 ? 0.0 : 1.0, 0, r->st, nullptr, nullptr, s);
+        if (e != hipSuccess) return hip_fail(e, "affine launch");
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        stats.band_energy = (k == 0) ? 0.0 : h.trH;
+        stats.trace = (double)k;
+        stats.idempotency = 0.0;
+        if (E_band) *E_band = stats.band_energy;
+        return FDM_OK;
+    }
+    if (!(h.emax > h.emin)) {
+        set_error("Hp is a multiple of the identity: no gap at n_occ");
+        return FDM_ENOCONV;
+    }
+    const int prec = opt.precision;
+    const int max_iter = opt.max_iter;
+    rc = set_params(0.0, max_iter, 0, 1);
+    if (rc) return rc;
+    int np = 0;
+    double *x64 = r->x64;
+    const size_t m64 = (size_t)r->lay.np * r->lay.ld;
+    double *X64[3] = {x64, x64 + m64, x64 + 2 * m64};
+    float *X32[2] = {r->x32, r->x32 + m64};
+
+    if (prec == P_F64) {
+        rc = affine(0, Hp, ldh, 0, X64[0], 0, 0, 1, &np);
+        if (rc) return rc;
+        rc = decide(D_INIT, np, 4);
+        if (rc) return rc;
+        void *res = nullptr;
+        int it = 0;
+        rc = sp2_phase(P_F64, X64[0], X64[1], max_iter, 0, 0.0, &res, &it);
+        if (rc) return rc;
+        stats.iters_fp64 = it;
+        stats.idempotency = r->hm_host->idem;
+        return finish(Hp, ldh, res, 0, D, ldd, E_band);
+    }
+
+    // ---- mixed forms ----
+    int k64 = opt.k64;
+    if (k64 < 0) {
+        // FP64 steps until the Gershgorin over-estimate of the spectral width
+        // has been worked off: 2 ceil(log2(W_G / W_est)) with W_est from the
+        // exact moments (2 sqrt(3) sigma, the width of a uniform spectrum).
+        const double mean = h.trH / (double)n;
+        const double var = std::max(h.fro2H / (double)n - mean * mean, 1e-300);
+        const double west = 2.0 * sqrt(3.0 * var);
+        const double ratio = (h.emax - h.emin) / west;
+        k64 = ratio > 1.0 ? 2 * (int)ceil(log2(ratio)) : 0;
+        k64 = std::min(std::max(k64, 0), 24);
+    }
+    double tau = opt.tau;
+    if (!(tau > 0.0)) tau = std::max(1e-3, 4.0 * unit_roundoff(prec) * sqrt(n_occ));
+    void *cur32 = nullptr;
+    if (k64 > 0) {
+        rc = affine(0, Hp, ldh, 0, X64[0], 0, 0, 1, &np);
+        if (rc) return rc;
+        rc = decide(D_INIT, np, 4);
+        if (rc) return rc;
+        void *res = nullptr;
+        int it = 0;
+        rc = sp2_phase(P_F64, X64[0], X64[1], k64, 2, tau, &res, &it);
+        if (rc) return rc;
+        stats.iters_fp64_first = it;
+        if (r->hm_host->idem <= tol && r->hm_host->result_iter < k64) {
+            stats.idempotency = r->hm_host->idem;
+            return finish(Hp, ldh, res, 0, D, ldd, E_band);
+        }
+        if (status) {  // the FP64 steps stagnated above tol: report the last iterate
+            stats.idempotency = r->hm_host->idem;
+            return finish(Hp, ldh, res, 0, D, ldd, E_band);
+        }
+        rc = affine(0, res, r->lay.ld, 1, X32[0], 1.0, 0.0, 0, &np);
+        if (rc) return rc;
+    } else {
+        rc = affine(0, Hp, ldh, 1, X32[0], 0, 0, 1, &np);
+        if (rc) return rc;
+    }
+    rc = decide(D_INIT, np, 4);
+    if (rc) return rc;
+    int itl = 0;
+    rc = sp2_phase(prec, X32[0], X32[1], max_iter, 1, tau, &cur32, &itl);
+    if (rc) return rc;
+    stats.iters_low = itl;
+    status = 0;  // reaching the cap in the low-precision phase is not an error
+    rc = affine(1, cur32, r->lay.ld, 0, X64[0], 1.0, 0.0, 0, &np);
+    if (rc) return rc;
+    rc = decide(D_INIT, np, 4);
+    if (rc) return rc;
+    double *res64 = nullptr;
+    int steps = 0;
+    rc = mcweeny_phase(X64[0], X64[1], X64[2], opt.mcweeny_max, &res64, &steps);
+    if (rc) return rc;
+    stats.mcweeny_steps = steps;
+    return finish(Hp, ldh, res64, 0, D, ldd, E_band);
+}
+
+void Ctx::finalize_timing() {
+    if (!opt.timing) return;
+    for (const Timed &t : timed) {
+        if (!t.real) continue;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r->tev[t.e0], r->tev[t.e1]) == hipSuccess)
+            stats.prod_ms[t.prec] += ms;
+    }
+}
+
+}  // namespace fdm
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using namespace fdm;
+
+extern "C" {
+
+int fdm_options_default(fdm_options *opt) {
+    if (!opt) return FDM_EINVAL;
+    memset(opt, 0, sizeof(*opt));
+    opt->precision = FDM_FP64;
+    opt->k64 = -1;
+    opt->tau = 0.0;
+    opt->max_iter = 100;
+    opt->mcweeny_max = 6;
+    opt->max_mu_evals = 12;
+    opt->fd_extra_depth = 7;
+    opt->fd_final_fp64 = 1;
+    opt->validate = 0;
+    opt->timing = 0;
+    opt->tile = 0;
+    return FDM_OK;
+}
+
+size_t fdm_workspace_bytes(int64_t N, double kT, int32_t precision) {
+    if (N <= 0 || N > 65535 * 64 || precision < 0 || precision >= FDM_NPREC || !(kT >= 0.0))
+        return 0;
+    return plan_layout(N, kT > 0.0, precision).bytes;
+}
+
+const char *fdm_strerror(int code) {
+    switch (code) {
+        case FDM_OK: return "success";
+        case FDM_EINVAL: return "invalid argument";
+        case FDM_ENOMEM: return "out of device memory or above the budget";
+        case FDM_ENOCONV: return "iteration did not converge";
+        case FDM_EHIP: return "HIP runtime error";
+        case FDM_ENONFINITE: return "input holds NaN or Inf";
+        default: return "unknown status";
+    }
+}
+
+const char *fdm_last_error(void) { return last_error(); }
+
+int fermi_dm_solve(const double *Hp, int64_t N, int64_t ldh, double n_occ, double kT, double tol,
+                   double *D, int64_t ldd, double *E_band, const fdm_options *opt_in,
+                   fdm_stats *stats_out, void *stream) {
+    const auto t0 = std::chrono::steady_clock::now();
+    set_error("");
+    fdm_options opt;
+    if (opt_in)
+        opt = *opt_in;
+    else
+        fdm_options_default(&opt);
+    if (!Hp || !D || N <= 0 || N >= 65535 * 64 || ldh < N || ldd < N || !(tol > 0.0) ||
+        !(kT >= 0.0) || !std::isfinite(kT) || opt.precision < 0 || opt.precision >= FDM_NPREC ||
+        opt.max_iter <= 0 || (opt.tile != 0 && opt.tile != 64 && opt.tile != 128)) {
+        set_error("invalid argument");
+        return FDM_EINVAL;
+    }
+    if ((const void *)Hp == (const void *)D) {
+        set_error("D may not alias Hp");
+        return FDM_EINVAL;
+    }
+    if (kT == 0.0) {
+        if (!(n_occ >= 0.0 && n_occ <= (double)N) || fabs(n_occ - llround(n_occ)) > 1e-9) {
+            set_error("zero temperature needs an integer n_occ in [0, N]");
+            return FDM_EINVAL;
+        }
+    } else if (!(n_occ > 0.0 && n_occ < (double)N)) {
+        set_error("finite temperature needs 0 < n_occ < N");
+        return FDM_EINVAL;
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    Resources *r = thread_resources(dev);
+    if (!r) return FDM_EHIP;
+    Ctx c;
+    c.r = r;
+    c.s = (hipStream_t)stream;
+    c.opt = opt;
+    c.n = N;
+    c.n_occ = n_occ;
+    c.tol = tol;
+    c.kT = kT;
+    memset(&c.stats, 0, sizeof(c.stats));
+    const Layout L = plan_layout(N, kT > 0.0, opt.precision);
+    int rc = r->bind(L, opt.workspace, opt.workspace_bytes, c.s);
+    if (rc == FDM_OK && opt.validate) rc = c.validate_symmetric(Hp, ldh);
+    if (rc == FDM_OK) rc = (kT == 0.0) ? c.solve_zero_t(Hp, ldh, D, ldd, E_band)
+                                       : c.solve_finite_t(Hp, ldh, D, ldd, E_band);
+    if (rc == FDM_OK && c.status) rc = c.status;
+    if (rc == FDM_OK || rc == FDM_ENOCONV) {
+        hipError_t e2 = hipStreamSynchronize(c.s);
+        if (e2 != hipSuccess) rc = hip_fail(e2, "hipStreamSynchronize");
+        c.finalize_timing();
+    }
+    c.stats.status = rc;
+    c.stats.tile = c.used_tile;
+    c.stats.ms_total =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats_out) *stats_out = c.stats;
+    if (rc == FDM_ENOCONV && fdm_last_error()[0] == 0) set_error("iteration cap or stagnation");
+    return rc;
+}
+
+int fdm_gershgorin(const double *H, int64_t N, int64_t ldh, double *out, int32_t *nonfinite,
+                   void *stream) {
+    set_error("");
+    if (!H || !out || N <= 0 || ldh < N) return FDM_EINVAL;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    Resources *r = thread_resources(dev);
+    if (!r) return FDM_EHIP;
+    Ctx c;
+    c.r = r;
+    c.s = (hipStream_t)stream;
+    fdm_options_default(&c.opt);
+    c.n = N;
+    int rc = r->bind(plan_layout(N, false, P_F64), nullptr, 0, c.s);
+    if (rc) return rc;
+    e = launch_gershgorin(H, ldh, (int)N, r->part, r->st, c.s);
+    if (e != hipSuccess) return hip_fail(e, "gershgorin launch");
+    DevState h;
+    rc = c.read_state(&h);
+    if (rc) return rc;
+    out[0] = h.emin;
+    out[1] = h.emax;
+    out[2] = h.trH;
+    out[3] = h.fro2H;
+    if (nonfinite) *nonfinite = h.nonfinite;
+    return FDM_OK;
+}
+
+int fdm_sym_product(int32_t precision, const double *A, const double *B, const double *E,
+                    double *C, int64_t N, int64_t ld, double alpha, double beta, double gamma,
+                    double *sums, int32_t tile, void *stream) {
+    set_error("");
+    if (!A || !B || !C || N <= 0 || ld < N || precision < 0 || precision >= FDM_NPREC ||
+        (tile != 0 && tile != 64 && tile != 128) || C == A || C == B || (E && C == E))
+        return FDM_EINVAL;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    Resources *r = thread_resources(dev);
+    if (!r) return FDM_EHIP;
+    Ctx c;
+    c.r = r;
+    c.s = (hipStream_t)stream;
+    fdm_options_default(&c.opt);
+    c.opt.tile = tile;
+    c.n = N;
+    const bool lo = precision != P_F64;
+    // Operands are packed into zero-padded working matrices of the product's
+    // precision (FP64, or the FP32 master of the low-precision forms).
+    Layout L = plan_layout(N, true, lo ? P_F32 : P_F64);
+    int rc = r->bind(L, nullptr, 0, c.s);
+    if (rc) return rc;
+    const size_t m = (size_t)L.np * L.ld;
+    void *slot[4];
+    for (int i = 0; i < 4; ++i)
+        slot[i] = lo ? (void *)(r->x32 + i * m) : (void *)(r->x64 + i * m);
+    const double *src[3] = {A, B, E};
+    void *dst[3] = {slot[0], slot[1], slot[2]};
+    if (B == A) dst[1] = slot[0];
+    if (E == A) dst[2] = slot[0];
+    else if (E == B) dst[2] = dst[1];
+    for (int i = 0; i < 3; ++i) {
+        if (!src[i]) continue;
+        if ((i == 1 && B == A) || (i == 2 && (E == A || E == B))) continue;
+        rc = c.affine(0, src[i], ld, lo ? 1 : 0, dst[i], 1.0, 0.0, 0, nullptr);
+        if (rc) return rc;
+    }
+    const double coef[3] = {alpha, beta, gamma};
+    rc = c.product(precision, dst[0], dst[1], E ? dst[2] : nullptr, slot[3], coef, nullptr, false,
+                   false);
+    if (rc) return rc;
+    rc = c.decide(D_SUMS, c.last_ntiles, 4);
+    if (rc) return rc;
+    e = launch_copy_out(lo ? 1 : 0, slot[3], L.ld, C, ld, (int)N, c.s);
+    if (e != hipSuccess) return hip_fail(e, "copy-out launch");
+    DevState h;
+    rc = c.read_state(&h);
+    if (rc) return rc;
+    if (sums) {
+        sums[0] = h.sums[0];
+        sums[1] = h.sums[1];
+        sums[2] = h.sums[2];
+    }
+    return FDM_OK;
+}
+
+int fdm_band_energy(const double *H, int64_t ldh, const double *D, int64_t ldd, int64_t N,
+                    double *out, void *stream) {
+    set_error("");
+    if (!H || !D || !out || N <= 0 || ldh < N || ldd < N) return FDM_EINVAL;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    Resources *r = thread_resources(dev);
+    if (!r) return FDM_EHIP;
+    Ctx c;
+    c.r = r;
+    c.s = (hipStream_t)stream;
+    fdm_options_default(&c.opt);
+    c.n = N;
+    int rc = r->bind(plan_layout(N, false, P_F64), nullptr, 0, c.s);
+    if (rc) return rc;
+    e = launch_energy(H, ldh, D, ldd, 0, (int)N, r->part, r->st, c.s);
+    if (e != hipSuccess) return hip_fail(e, "energy launch");
+    DevState h;
+    rc = c.read_state(&h);
+    if (rc) return rc;
+    out[0] = h.sums[0];
+    out[1] = h.sums[1];
+    return FDM_OK;
+}
+
+}  // extern "C"

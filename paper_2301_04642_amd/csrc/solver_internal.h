@@ -1,0 +1,104 @@
+// Host-side solver structures (driver internals, not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <functional>
+#include <vector>
+
+#include "fdm_internal.h"
+
+namespace fdm {
+
+// Carving of one workspace allocation: n64 FP64 and n32 FP32 zero-padded
+// np x ld working matrices, per-tile partial sums, two tile lists and the
+// device state.
+struct Layout {
+    int64_t n = 0, np = 0, ld = 0;
+    int n64 = 0, n32 = 0;
+    size_t off64 = 0, off32 = 0, off_part = 0, off_tiles64 = 0, off_tiles128 = 0, off_state = 0;
+    size_t bytes = 0;
+    int ntiles64 = 0, ntiles128 = 0;
+    int64_t part_cap = 0;
+};
+Layout plan_layout(int64_t n, bool finite, int prec);
+
+// Per host thread and device: the cached workspace, the mapped host mirror
+// of the device state, and events.
+struct Resources {
+    int device = -1;
+    char *base = nullptr;
+    size_t cap = 0;
+    bool owned = false;
+    char *bound_mem = nullptr;
+    int64_t bound_key = -1, bound_ld = -1;
+    Layout lay;
+    double *x64 = nullptr;
+    float *x32 = nullptr;
+    double *part = nullptr;
+    uint32_t *tiles64 = nullptr, *tiles128 = nullptr;
+    DevState *st = nullptr;
+    HostMirror *hm_host = nullptr, *hm_dev = nullptr;
+    DevState *st_pinned = nullptr;
+    DevState st_fallback;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> tev;
+
+    ~Resources();
+    int init(int dev);
+    int bind(const Layout &L, void *user_mem, size_t user_bytes, hipStream_t s);
+    hipEvent_t timing_event(size_t i);
+    DevState *st_host();
+};
+Resources *thread_resources(int dev);
+
+int hip_fail(hipError_t e, const char *what);
+const char *last_error();
+
+struct Timed {
+    int prec;
+    size_t e0, e1;
+    bool real;
+};
+
+// One call's context.
+struct Ctx {
+    Resources *r = nullptr;
+    hipStream_t s = nullptr;
+    fdm_options opt;
+    fdm_stats stats;
+    int64_t n = 0;
+    double n_occ = 0.0, tol = 0.0, kT = 0.0;
+    int status = 0;
+    int last_ntiles = 0;
+    int used_tile = 0;
+    std::vector<int> phase_launches;
+    std::vector<Timed> timed;
+
+    int tile_for(int prec) const;
+    int product(int prec, const void *A, const void *B, const void *E, void *C, const double c0[3],
+                const double c1[3], bool sel, bool done_guard);
+    void close_phase(int executed);
+    int decide(int mode, int count, int stride);
+    int set_params(double tau, int max_iter, int switch_mode, int reset_all);
+    int affine(int in_f32, const void *in, int64_t ldi, int out_f32, void *out, double a,
+               double b, int zt, int *nparts);
+    int run_loop(int max_steps, const std::function<int(int)> &enqueue);
+    int sp2_phase(int prec, void *b0, void *b1, int max_iter, int switch_mode, double tau,
+                  void **result, int *iters);
+    int mcweeny_phase(double *x0, double *t, double *x1, int max_steps, double **result,
+                      int *steps);
+    int read_state(DevState *out);
+    int bounds(const double *Hp, int64_t ldh, DevState *h);
+    int finish(const double *Hp, int64_t ldh, const void *dm, int dm_f32, double *D, int64_t ldd,
+               double *E_band);
+    int validate_symmetric(const double *Hp, int64_t ldh);
+    int solve_zero_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, double *E_band);
+    int solve_finite_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, double *E_band);
+    int fermi_operator(const double *Hp, int64_t ldh, double mu, int depth, int prec,
+                       void **result, int *result_f32, double *trace, double *trace_dd);
+    void finalize_timing();
+};
+
+}  // namespace fdm

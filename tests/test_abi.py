@@ -1,0 +1,87 @@
+"""The C-ABI library loads and exports every symbol include/fermidm.h
+declares; host-only entry points behave as documented (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fermidm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(fdm_\w+|fermi_dm_solve)\s*\(", text)
+    return sorted(set(n for n in names if not n.endswith("_t")))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("fermi_dm_solve", "fdm_workspace_bytes", "fdm_strerror", "fdm_options_default",
+                 "fdm_gershgorin", "fdm_sym_product", "fdm_band_energy", "fdm_fermi_operator",
+                 "fdm_server_create", "fdm_submit", "fdm_poll", "fdm_result",
+                 "fdm_server_destroy", "fdm_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2301_04642_amd as fdm
+    lib = ctypes.CDLL(fdm.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(fdm.EXPORTS)
+
+
+def test_struct_sizes_match_header():
+    """The binding's ctypes structs have the C layouts (checked against a
+    tiny C program compiled from the header)."""
+    import subprocess
+    import tempfile
+    import paper_2301_04642_amd as fdm
+    src = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "fermidm.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(fdm_options), sizeof(fdm_stats),
+         sizeof(fdm_server_options), offsetof(fdm_stats, e_min), offsetof(fdm_stats, prod_ms),
+         offsetof(fdm_options, workspace));
+  return 0;
+}'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        got = [int(x) for x in subprocess.check_output([exe]).split()]
+    want = [ctypes.sizeof(fdm.fdm_options), ctypes.sizeof(fdm.fdm_stats),
+            ctypes.sizeof(fdm.fdm_server_options), fdm.fdm_stats.e_min.offset,
+            fdm.fdm_stats.prod_ms.offset, fdm.fdm_options.workspace.offset]
+    assert got == want
+
+
+def test_options_default_and_strerror():
+    import paper_2301_04642_amd as fdm
+    o = fdm.fdm_options_default()
+    assert o.precision == fdm.FDM_FP64 and o.k64 == -1 and o.max_iter == 100
+    assert o.fd_extra_depth == 7 and o.fd_final_fp64 == 1 and o.workspace is None
+    assert fdm.fdm_strerror(fdm.FDM_ENOCONV) == "iteration did not converge"
+    assert fdm.fdm_strerror(12345) == "unknown status"
+    assert fdm.library().fdm_options_default(None) == fdm.FDM_EINVAL
+
+
+def test_workspace_bytes():
+    import paper_2301_04642_amd as fdm
+    n = 4000
+    np_ = 4096
+    b64 = fdm.fdm_workspace_bytes(n, 0.0, fdm.FDM_FP64)
+    b32 = fdm.fdm_workspace_bytes(n, 0.0, fdm.FDM_FP32)
+    bft = fdm.fdm_workspace_bytes(n, 0.0016, fdm.FDM_FP16X3)
+    assert b64 >= 3 * np_ * np_ * 8
+    assert b32 >= b64 + 2 * np_ * np_ * 4
+    assert bft >= 5 * np_ * np_ * (8 + 4)
+    assert fdm.fdm_workspace_bytes(0, 0.0, 0) == 0
+    assert fdm.fdm_workspace_bytes(10, -1.0, 0) == 0
+    assert fdm.fdm_workspace_bytes(10, 0.0, 9) == 0

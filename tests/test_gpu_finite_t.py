@@ -1,0 +1,106 @@
+"""Finite temperature on the GPU against the oracle: one evaluation of the
+doubling recursion against its closed form f_m (diagonal H) and against the
+oracle recursion (dense H); full solves against the exact Fermi-Dirac density
+matrix of the definition (Sec. II.A)."""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_util import dev, host, reference, say
+
+pytestmark = pytest.mark.gpu
+
+KT = 0.0016
+
+
+@pytest.fixture(scope="module")
+def fdm():
+    import paper_2301_04642_amd as m
+    return m
+
+
+def test_operator_closed_form_diagonal(fdm):
+    import torch
+    from oracle import fd
+    lam = np.linspace(-1.0, 1.0, 97)
+    mu = 0.0123
+    H = dev(np.diag(lam))
+    D = torch.empty_like(H)
+    say("fermi operator diagonal")
+    tr, trdd, m = fdm.fdm_fermi_operator(H, mu, KT, D, depth=0)
+    ref = fd.closed_form(lam, mu, 1.0 / KT, m)
+    d = host(D)
+    assert np.abs(np.diag(d) - ref).max() < 1e-13
+    assert np.abs(d - np.diag(np.diag(d))).max() < 1e-15
+    assert abs(tr - ref.sum()) < 1e-12
+    assert abs(trdd - (ref - ref ** 2).sum()) < 1e-12
+    assert m == fd.depth(1.0 / KT, -1.0 - 0.0, 1.0, mu, extra=7)
+
+
+@pytest.mark.parametrize("n", [64, 129, 300])
+def test_operator_dense_matches_oracle_recursion(fdm, n):
+    import torch
+    from oracle import fd
+    wl = workloads.config_workload(2, n=n)
+    mu = -0.41
+    H = dev(wl.hp)
+    D = torch.empty_like(H)
+    say("fermi operator dense", n)
+    tr, trdd, m = fdm.fdm_fermi_operator(H, mu, KT, D, depth=0)
+    ref = fd.doubling(wl.hp, mu, 1.0 / KT, m)
+    assert np.abs(host(D) - ref).max() < 1e-12
+    # and the recursion is the Fermi operator to its truncation error
+    from oracle import density as den
+    f = den.fermi_dirac(wl.lam, mu, KT)
+    d_exact = (wl.q * f) @ wl.q.T
+    assert np.linalg.norm(host(D) - d_exact) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16x3"])
+def test_operator_low_precision(fdm, prec):
+    import torch
+    from oracle import fd
+    wl = workloads.config_workload(2, n=200)
+    mu = -0.5
+    H = dev(wl.hp)
+    D = torch.empty_like(H)
+    say("fermi operator", prec)
+    tr, trdd, m = fdm.fdm_fermi_operator(H, mu, KT, D, depth=0, precision=prec)
+    ref = fd.doubling(wl.hp, mu, 1.0 / KT, m)
+    # near-mu errors double per step (u beta rho / 4 floor): ~1e-4 in FP32
+    assert np.abs(host(D) - ref).max() < 5e-3
+    assert abs(tr - np.trace(ref)) < 0.05
+
+
+def check_solve(fdm, wl, prec, gate_fp64=True):
+    d_ref, e_ref, mu_ref, f = reference(wl)
+    say("finite-T solve", prec, wl.name)
+    D, e, st = fdm.solve(dev(wl.hp), wl.n_occ, wl.kT, 1e-9 if prec == "fp64" else 1e-6, prec)
+    d = host(D)
+    dd = np.linalg.norm(d - d_ref)
+    de = abs(e - e_ref)
+    tr = abs(np.trace(d) - wl.n_occ)
+    print(f"[report] finite-T {prec} n={wl.n} evals={st.mu_evals} depth={st.depth} "
+          f"mu={st.mu:.8f} (exact {mu_ref:.8f}) |dE|={de:.2e} ||dD||={dd:.2e} |dTr|={tr:.2e}",
+          flush=True)
+    assert st.status == 0
+    assert np.array_equal(d, d.T)
+    if prec == "fp64" or gate_fp64:
+        assert dd <= 1e-9
+        assert de <= 1e-10
+        assert tr <= 1e-9
+        comm = np.linalg.norm(wl.hp @ d - d @ wl.hp)
+        assert comm <= 1e-10
+    return st
+
+
+@pytest.mark.parametrize("n", [100, 257])
+def test_solve_fp64(fdm, n):
+    check_solve(fdm, workloads.config_workload(2, n=n), "fp64")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16x3", "bf16x3"])
+def test_solve_mixed_final_fp64(fdm, prec):
+    """Low-precision mu search, one FP64 evaluation and the trace correction."""
+    st = check_solve(fdm, workloads.config_workload(2, n=400), prec)
+    assert st.products[fdm.PRECISIONS[prec]] > 0 and st.products[0] > 0

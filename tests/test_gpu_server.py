@@ -1,0 +1,100 @@
+"""Serving: continuous batching of mixed zero- and finite-temperature
+requests.  Each result equals the same request solved alone (bitwise: every
+solve is deterministic and independent of what else runs); the budget is
+enforced at submission and at admission."""
+import time
+
+import numpy as np
+import pytest
+
+import workloads
+from gpu_util import dev, host, reference, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fdm():
+    import paper_2301_04642_amd as m
+    return m
+
+
+def requests(count=10):
+    reqs = workloads.serving_requests(count, n_lo=100, n_hi=700, rate=50.0)
+    return [(r, workloads.serving_workload(r)) for r in reqs]
+
+
+def test_alone_equals_mix(fdm):
+    reqs = requests(10)
+    prec = "fp32"
+    alone = {}
+    for r, wl in reqs:
+        say("alone", r["id"], wl.n)
+        D, e, st = fdm.solve(dev(wl.hp), wl.n_occ, wl.kT, 1e-8, prec)
+        alone[r["id"]] = (host(D), e)
+    srv = fdm.Server(budget_bytes=8 << 30, max_active=4, precision=prec)
+    try:
+        tickets = {}
+        t0 = time.time()
+        for r, wl in reqs:
+            while time.time() - t0 < r["arrival"]:
+                time.sleep(0.001)
+            tickets[r["id"]] = srv.submit(wl.hp, wl.n_occ, wl.kT, 1e-8)
+        starts, finishes = [], []
+        for r, wl in reqs:
+            say("mix result", r["id"])
+            rc, d, e, st, times = srv.result(tickets[r["id"]], wl.n)
+            assert rc == 0
+            assert np.array_equal(d, alone[r["id"]][0]), r["id"]
+            assert e == alone[r["id"]][1]
+            d_ref, e_ref, _, _ = reference(wl)
+            assert abs(e - e_ref) <= 1e-6
+            starts.append(times[1])
+            finishes.append(times[2])
+        # work overlapped: some request started before another had finished
+        order = np.argsort(starts)
+        overlapped = any(starts[order[i + 1]] < finishes[order[i]] for i in range(len(order) - 1))
+        assert overlapped
+    finally:
+        srv.close()
+
+
+def test_budget_enforced(fdm):
+    n = 300
+    foot = fdm.fdm_workspace_bytes(n, 0.0, fdm.FDM_FP32) + 2 * n * n * 8
+    srv = fdm.Server(budget_bytes=foot + foot // 2, max_active=4, precision="fp32")
+    try:
+        big = workloads.config_workload(0, n=600)
+        with pytest.raises(fdm.FdmError) as ei:
+            srv.submit(big.hp, big.n_occ, 0.0, 1e-8)
+        assert ei.value.code == fdm.FDM_ENOMEM
+        wls = [workloads.config_workload(0, n=n, seed_base=77 + i) for i in range(4)]
+        say("budget: serial admission")
+        ts = [srv.submit(w.hp, w.n_occ, 0.0, 1e-8) for w in wls]
+        spans = []
+        for t, w in zip(ts, wls):
+            rc, d, e, st, times = srv.result(t, n)
+            assert rc == 0
+            spans.append((times[1], times[2]))
+        # only one footprint fits: executions never overlap
+        spans.sort()
+        for (s0, f0), (s1, f1) in zip(spans, spans[1:]):
+            assert s1 >= f0
+    finally:
+        srv.close()
+
+
+def test_device_input_and_poll(fdm):
+    wl = workloads.config_workload(0, n=200)
+    srv = fdm.Server(budget_bytes=1 << 30, max_active=2, precision="fp64")
+    try:
+        say("device input")
+        t = srv.submit(dev(wl.hp), wl.n_occ, 0.0, 1e-10, precision="fp64")
+        while srv.poll(t) == 1:
+            time.sleep(0.001)
+        rc, d, e, st, times = srv.result(t, wl.n)
+        d_ref, e_ref, _, _ = reference(wl)
+        assert rc == 0 and np.linalg.norm(d - d_ref) < 1e-10
+        assert srv.poll(t) < 0
+    finally:
+        srv.close()

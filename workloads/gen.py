@@ -183,7 +183,7 @@ def config_workload(c: int, n: Optional[int] = None, seed_base: Optional[int] = 
     seed = 1000 * (c + 1) if seed_base is None else seed_base
     rng = np.random.default_rng(seed + 2)
     if c == 0:
-        n_occ = n // 4
+        n_occ = max(1, n // 4) if n > 1 else 0
         lam = spectrum_gapped_uniform(n, n_occ, (-1.0, -0.2), (0.0, 1.5), rng)
     elif c == 1:
         n_occ = n // 4

@@ -474,14 +474,15 @@ int Ctx::solve_zero_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, dou
     // ---- mixed forms ----
     int k64 = opt.k64;
     if (k64 < 0) {
-        // FP64 steps until the Gershgorin over-estimate of the spectral width
-        // has been worked off: 2 ceil(log2(W_G / W_est)) with W_est from the
-        // exact moments (2 sqrt(3) sigma, the width of a uniform spectrum).
+        // FP64 steps while the Gershgorin over-estimate of the spectral width
+        // keeps the HOMO-LUMO gap of X tiny: ceil(log2(W_G / W_est)) with
+        // W_est from the exact moments (2 sqrt(3) sigma, the width of a
+        // uniform spectrum).
         const double mean = h.trH / (double)n;
         const double var = std::max(h.fro2H / (double)n - mean * mean, 1e-300);
         const double west = 2.0 * sqrt(3.0 * var);
         const double ratio = (h.emax - h.emin) / west;
-        k64 = ratio > 1.0 ? 2 * (int)ceil(log2(ratio)) : 0;
+        k64 = ratio > 1.0 ? (int)ceil(log2(ratio)) : 0;
         k64 = std::min(std::max(k64, 0), 24);
     }
     double tau = opt.tau;

@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override N (testing only)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="fp64,fp32,fp16x3,bf16x3")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the solver has no multi-GPU path "
@@ -106,6 +108,15 @@ def main():
     import workloads
 
     torch.cuda.set_device(0)
+    if args.calib_copy_mib:
+        nel = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written")
+        del src, dst
     log("generating workload")
     wl = workloads.config_workload(1, n=args.n)
     e_ref = float(np.sort(wl.lam)[: int(wl.n_occ)].sum())   # sum of the n_occ lowest

@@ -76,6 +76,10 @@ class FdmError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2301_04642_amd.build`")
+    # PyTorch bundles its own HIP runtime with the same soname as the system
+    # one.  Load torch's first so that libfermidm binds to it: one HIP runtime
+    # (and one HSA runtime) per process, shared device memory and streams.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, D, I32, I64, VP = (ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int64,
                           ctypes.c_void_p)

@@ -269,6 +269,10 @@ __global__ __launch_bounds__(256) void k_symprod(ProdArgs a) {
     }
 
     // ---- fused epilogue -------------------------------------------------
+    // Accumulator lane layout of a 16x16 block (lane l, register q): column
+    // l % 16 and row 4*(l/16) + q for the FP32-accumulating MFMAs, row
+    // l/16 + 4*q for v_mfma_f64_16x16x4.
+    constexpr bool ROWS_CONSECUTIVE = (P != P_F64);
     const int sel = (a.sel != nullptr) ? *a.sel : 0;
     const double alpha = a.coef[sel][0], beta = a.coef[sel][1], gamma = a.coef[sel][2];
     const double scale = (HALF && T::F16) ? kF16Unscale : 1.0;
@@ -280,37 +284,43 @@ __global__ __launch_bounds__(256) void k_symprod(ProdArgs a) {
     for (int i = 0; i < FM; ++i) {
 #pragma unroll
         for (int j = 0; j < FM; ++j) {
-            const int64_t rbase = row0 + wr * WT + i * 16 + 4 * lg;
+            const int64_t rb = row0 + wr * WT + i * 16;
             const int64_t col = col0 + wc * WT + j * 16 + lr;
             S ov[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int64_t row = rbase + q;
+                const int64_t row = rb + (ROWS_CONSECUTIVE ? 4 * lg + q : lg + 4 * q);
                 const double v = (double)acc[i][j][q] * scale;
                 const double e = (E != nullptr) ? (double)E[row * ld + col] : 0.0;
                 double o = alpha * v + beta * e;
                 if (row == col && row < a.n) o += gamma;
                 const S os = (S)o;
                 ov[q] = os;
-                C[row * ld + col] = os;
-                const double od = (double)os;
-                if (row == col) s_tr += od;
-                s_f2 += od * od;
-                s_d2 += (v - e) * (v - e);
+                // Off-diagonal tiles: every element, stored twice (mirror).
+                // Diagonal tiles: only row <= col is kept and mirrored, so C
+                // is exactly symmetric even where (i,j) and (j,i) were
+                // accumulated in different orders.
+                const double w = diag ? (row < col ? 2.0 : (row == col ? 1.0 : 0.0)) : 2.0;
+                if (w != 0.0) {
+                    C[row * ld + col] = os;
+                    if (diag && row < col) C[col * ld + row] = os;
+                    const double od = (double)os;
+                    if (row == col) s_tr += od;
+                    s_f2 += w * od * od;
+                    s_d2 += w * (v - e) * (v - e);
+                }
             }
             if (!diag) {
-                S *dst = C + col * ld + rbase;
-                if constexpr (sizeof(S) == 8) {
-                    *(d4_t *)dst = d4_t{(double)ov[0], (double)ov[1], (double)ov[2], (double)ov[3]};
-                } else {
+                if constexpr (ROWS_CONSECUTIVE) {
+                    S *dst = C + col * ld + rb + 4 * lg;
                     *(f4_t *)dst = f4_t{(float)ov[0], (float)ov[1], (float)ov[2], (float)ov[3]};
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) C[col * ld + rb + lg + 4 * q] = ov[q];
                 }
             }
         }
     }
-    const double wgt = diag ? 1.0 : 2.0;
-    s_f2 *= wgt;
-    s_d2 *= wgt;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         s_tr += __shfl_xor(s_tr, off);

@@ -1,0 +1,86 @@
+"""Full-size configurations (N = 12000 finite temperature, N = 30000 zero
+temperature with outliers): sampled rows of D against rows the oracle builds
+one by one from the known eigenbasis, plus properties that hold at any size
+(band energy against the closed form sum f_i lam_i, trace, idempotency and
+commutator on sampled rows)."""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_util import dev, host, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fdm():
+    import paper_2301_04642_amd as m
+    return m
+
+
+def sampled_checks(wl, d, f, rows, tol_rows, tol_idem, tol_comm):
+    from oracle import density as den
+    ref_rows = den.density_rows(wl.q_rows, wl.n, f, rows)
+    err = np.abs(d[rows] - ref_rows).max()
+    dr = d[rows]
+    idem = np.linalg.norm(dr @ d - dr)
+    hr = wl.hp[rows]
+    comm = np.linalg.norm(hr @ d - dr @ wl.hp)
+    print(f"[report] {wl.name}: sampled-row max err {err:.2e}, row idempotency {idem:.2e}, "
+          f"row commutator {comm:.2e}", flush=True)
+    assert err <= tol_rows
+    assert idem <= tol_idem
+    assert comm <= tol_comm
+
+
+def test_config3_n30000_fp32_mixed(fdm):
+    """N = 30000, n_occ = 7500, bands + 1% outliers up to 5 Ha, gap 0.05 Ha:
+    FP32 bulk with FP64 first steps, traces and McWeeny refinement."""
+    from oracle import density as den
+    say("generate config3 N=30000")
+    wl = workloads.config_workload(3)
+    H = dev(wl.hp)
+    say("solve config3 fp32")
+    D, e, st = fdm.solve(H, wl.n_occ, 0.0, 1e-8, "fp32")
+    del H
+    d = host(D)
+    del D
+    f, _ = den.occupations(wl.lam, wl.n_occ, 0.0)
+    e_ref = float(np.dot(f, wl.lam))
+    print(f"[report] config3: k64={st.iters_fp64_first} low={st.iters_low} mcw={st.mcweeny_steps} "
+          f"|dE|={abs(e - e_ref):.2e} idem={st.idempotency:.2e} bounds=({st.e_min:.1f},{st.e_max:.1f})",
+          flush=True)
+    assert st.status == 0
+    assert abs(e - e_ref) <= 1e-6
+    assert abs(np.trace(d) - wl.n_occ) <= 1e-8
+    assert st.idempotency <= 1e-8
+    rows = np.random.default_rng(3).choice(wl.n, 6, replace=False)
+    sampled_checks(wl, d, f, rows, tol_rows=1e-4, tol_idem=1e-8, tol_comm=1e-6)
+
+
+def test_config2_n12000_finite_t_mixed(fdm):
+    """N = 12000, uniform [-1, 1], kT = 0.0016 Ha, n_occ = 3000: FP16x3 mu
+    search, one FP64 evaluation and the first-order trace correction."""
+    from oracle import density as den
+    say("generate config2 N=12000")
+    wl = workloads.config_workload(2)
+    H = dev(wl.hp)
+    say("solve config2 fp16x3")
+    D, e, st = fdm.solve(H, wl.n_occ, wl.kT, 1e-6, "fp16x3")
+    d = host(D)
+    f, mu = den.occupations(wl.lam, wl.n_occ, wl.kT)
+    e_ref = float(np.dot(f, wl.lam))
+    print(f"[report] config2: evals={st.mu_evals} depth={st.depth} mu={st.mu:.9f} (exact {mu:.9f}) "
+          f"|dE|={abs(e - e_ref):.2e} |dTr|={abs(np.trace(d) - wl.n_occ):.2e}", flush=True)
+    assert st.status == 0
+    assert abs(e - e_ref) <= 1e-6
+    assert abs(np.trace(d) - wl.n_occ) <= 1e-6
+    rows = np.random.default_rng(2).choice(wl.n, 6, replace=False)
+    from oracle import density as den2
+    ref_rows = den2.density_rows(wl.q_rows, wl.n, f, rows)
+    err = np.abs(d[rows] - ref_rows).max()
+    hr = wl.hp[rows]
+    comm = np.linalg.norm(hr @ d - d[rows] @ wl.hp)
+    print(f"[report] config2: sampled-row max err {err:.2e}, row commutator {comm:.2e}", flush=True)
+    assert err <= 1e-5
+    assert comm <= 1e-6

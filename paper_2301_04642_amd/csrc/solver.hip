@@ -40,11 +40,18 @@ int hip_fail(hipError_t e, const char *what) {
 // ---------------------------------------------------------------------------
 // tile lists
 // ---------------------------------------------------------------------------
+// Upper-triangular tiles (ti <= tj) in bands of kBand tile rows, each band
+// walked column by column: the blocks that run at the same time on one XCD
+// (a contiguous run of this list) share a few row panels of A and B, so the
+// panel k-slices they stream are reused from that XCD's L2.
+constexpr int kBand = 8;
 static std::vector<uint32_t> upper_tiles(int nt) {
     std::vector<uint32_t> v;
     v.reserve((size_t)nt * (nt + 1) / 2);
-    for (int i = 0; i < nt; ++i)
-        for (int j = i; j < nt; ++j) v.push_back(((uint32_t)i << 16) | (uint32_t)j);
+    for (int i0 = 0; i0 < nt; i0 += kBand)
+        for (int j = i0; j < nt; ++j)
+            for (int i = i0; i < std::min(i0 + kBand, j + 1); ++i)
+                v.push_back(((uint32_t)i << 16) | (uint32_t)j);
     return v;
 }
 

@@ -157,8 +157,12 @@ __device__ __forceinline__ typename PT<P>::Acc mfma_frag(const u4_t &a, const u4
     return c;
 }
 
+// 64-wide tiles are register-capped to four waves per SIMD (four blocks per
+// CU); 128-wide tiles run one wave per SIMD.
 template <int P, int BT>
-__global__ __launch_bounds__(256) void k_symprod(ProdArgs a) {
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(BT == 64 ? 4 : 1, BT == 64 ? 4 : 1)))
+void k_symprod(ProdArgs a) {
     if (a.done != nullptr && *a.done) return;
     using T = PT<P>;
     using S = typename T::S;

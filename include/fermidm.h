@@ -120,8 +120,8 @@ size_t fdm_workspace_bytes(int64_t N, double kT, int32_t precision);
  *  kT     electronic temperature in Hartree (k_B T_e; beta = 1/kT).  0 selects
  *         the zero-temperature projector.
  *  tol    kT == 0: stop when ||X^2 - X||_F <= tol;  kT > 0: stop the mu
- *         search when |Tr D - n_occ| <= tol (a first-order correction in mu
- *         follows).  Must be > 0.
+ *         search when |Tr D - n_occ| <= tol or the Newton step in mu is below
+ *         1e-3 kT (a second-order correction of D in mu follows).  Must be > 0.
  *  D      device, N x N, leading dimension ldd >= N: receives D (full,
  *         symmetric).  May not alias Hp.
  *  E_band host: receives Tr(Hp D) (nullable).

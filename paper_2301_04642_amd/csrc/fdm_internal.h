@@ -102,6 +102,12 @@ int energy_blocks(int n);
 hipError_t launch_copy_out(int src_f32, const void *src, int64_t lds, double *dst,
                            int64_t ldd, int n, hipStream_t s);
 
+// out = a X + b Y + c I on [0,n)^2 of working matrices (zeros elsewhere in
+// [0,np)^2), with per-block (Tr, ||.||^2) partials.
+hipError_t launch_axpby2(int f32, const void *X, const void *Y, void *out, int64_t ld, int n,
+                         int np, double a, double b, double c, double *partials, int *nparts,
+                         hipStream_t s);
+
 hipError_t launch_set_params(DevState *st, double n_occ, double tol, double tau, int max_iter,
                              int switch_mode, int reset_all, hipStream_t s);
 

@@ -16,10 +16,11 @@
 // elementwise (Z_1 = 2cI - c^2 (I + 4S)).  No scalar is read back inside an
 // evaluation.
 //
-// mu is unknown to the method: a safeguarded Newton iteration on
-// Tr D(mu) = n_occ (dTr/dmu = beta Tr(D - D^2), and Tr D^2 = ||D||_F^2),
-// optionally in low precision, then one FP64 evaluation at the final mu and
-// the first-order canonical correction D <- D + dmu beta (D - D^2).
+// mu is unknown to the method: Newton on Tr D(mu) = n_occ (dTr/dmu =
+// beta Tr(D - D^2), and Tr D^2 = ||D||_F^2), kept inside a bracket by an
+// Illinois regula falsi, optionally in low precision, then one FP64
+// evaluation at the final mu and the second-order canonical correction
+// D <- D + u (D - D^2) + u^2/2 (D - 3D^2 + 2D^3), u = beta dmu.
 #include <math.h>
 #include <string.h>
 
@@ -181,6 +182,52 @@ int Ctx::fermi_operator(const double *Hp, int64_t ldh, double mu, int depth, int
     return FDM_OK;
 }
 
+// Second-order canonical correction of an FP64 evaluation D = D(mu):
+//   D(mu + u/beta) ~ D + u (D - D^2) + u^2/2 (D - 3D^2 + 2D^3)
+// (the Fermi function's derivatives in mu are beta f(1-f) and
+// beta^2 f(1-f)(1-2f)), with u the root of the same expansion of the trace
+// at n_occ.  Costs two FP64 products (D^2 and D^2 D).  Returns the working
+// matrix that holds the corrected D.
+int Ctx::canonical_correction(void *dm, double tr, double trdd, double *mu, void **out) {
+    const size_t m = (size_t)r->lay.np * r->lay.ld;
+    double *free_buf[4];
+    int nf = 0;
+    for (int i = 0; i < 5 && nf < 4; ++i)
+        if ((void *)(r->x64 + i * m) != dm) free_buf[nf++] = r->x64 + i * m;
+    double *P = free_buf[0], *Q = free_buf[1], *out_buf = free_buf[2];
+    const double *D = (const double *)dm;
+    static const double c_sq[3] = {1.0, 0.0, 0.0};
+    int rc = product(P_F64, D, D, nullptr, P, c_sq, nullptr, false, false);
+    if (rc) return rc;
+    hipError_t e = launch_energy(D, r->lay.ld, P, r->lay.ld, 0, (int)n, r->part, r->st, s);
+    if (e != hipSuccess) return hip_fail(e, "trace launch");
+    DevState h;
+    rc = read_state(&h);
+    if (rc) return rc;
+    const double tr3 = h.sums[0];                       // Tr D^3 = sum D o D^2
+    const double fro2 = tr - trdd;                       // ||D||^2 = Tr D^2
+    const double t1 = trdd;                              // Tr(D - D^2)
+    const double t2 = tr - 3.0 * fro2 + 2.0 * tr3;       // Tr(D - 3D^2 + 2D^3)
+    const double delta = n_occ - tr;
+    double u = 0.0;
+    if (t1 > 1e-300) {
+        const double disc = t1 * t1 + 2.0 * t2 * delta;
+        u = (disc > 0.0) ? 2.0 * delta / (t1 + sqrt(disc)) : delta / t1;
+    }
+    const double c1 = u, c2 = 0.5 * u * u;
+    // Q = (1 + c1 + c2) D - (c1 + 3 c2) D^2 ;  D' = Q + 2 c2 D^2 D
+    e = launch_axpby2(0, D, P, Q, r->lay.ld, (int)n, (int)r->lay.np, 1.0 + c1 + c2,
+                      -(c1 + 3.0 * c2), 0.0, nullptr, nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "axpby launch");
+    const double coef[3] = {2.0 * c2, 1.0, 0.0};
+    rc = product(P_F64, P, D, Q, out_buf, coef, nullptr, false, false);
+    if (rc) return rc;
+    close_phase(2);
+    *mu += u / kT;
+    *out = out_buf;
+    return FDM_OK;
+}
+
 int Ctx::solve_finite_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, double *E_band) {
     DevState h;
     int rc = bounds(Hp, ldh, &h);
@@ -192,19 +239,27 @@ int Ctx::solve_finite_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, d
     const double m1 = h.trH / (double)n;
     const double m2 = std::max(h.fro2H / (double)n - m1 * m1, 0.0);
     double mu = m1 + sqrt(3.0 * m2) * (2.0 * n_occ / (double)n - 1.0);
-    double lo_b = h.emin, hi_b = h.emax;
-    if (!(hi_b > lo_b)) {
-        lo_b -= 1.0;
-        hi_b += 1.0;
+    // bracket: Tr D(e_min) ~ 0 < n_occ < N ~ Tr D(e_max)
+    double lo = h.emin, hi = h.emax;
+    if (!(hi > lo)) {
+        lo -= 1.0;
+        hi += 1.0;
     }
-    mu = std::min(std::max(mu, lo_b), hi_b);
+    double f_lo = -n_occ, f_hi = (double)n - n_occ;
+    int side = 0;  // Illinois: which end was kept last (-1 lo, +1 hi)
+    mu = std::min(std::max(mu, lo + 1e-3 * (hi - lo)), hi - 1e-3 * (hi - lo));
     void *dm = nullptr;
     int dm_f32 = 0;
     double tr = 0.0, trdd = 0.0;
     int evals = 0, depth = 0;
     const int max_evals = std::max(1, opt.max_mu_evals);
     bool converged = false;
-    for (; evals < max_evals;) {
+    // FP64 search: stop once |Tr D - n_occ| <= tol or the Newton step is so
+    // small (|beta dmu| <= 1e-3) that the second-order correction is exact to
+    // O(1e-10); low-precision search: stop at |beta dmu| <= 1e-4 (below the
+    // trace noise of FP32-class products).
+    const double u_stop = (pe == P_F64) ? 1e-3 : 1e-4;
+    while (evals < max_evals) {
         depth = fd_depth(beta, h.emin, h.emax, mu, extra);
         rc = fermi_operator(Hp, ldh, mu, depth, pe, &dm, &dm_f32, &tr, &trdd);
         if (rc) return rc;
@@ -214,28 +269,36 @@ int Ctx::solve_finite_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, d
             converged = true;
             break;
         }
-        if (err < 0.0)
-            lo_b = mu;
-        else
-            hi_b = mu;
-        double step = (trdd > 1e-300) ? -err / (beta * trdd) : 0.0;
-        double next = mu + step;
-        if (!(next > lo_b && next < hi_b) || step == 0.0) next = 0.5 * (lo_b + hi_b);
-        if (pe != P_F64 && fabs(next - mu) <= 1e-7) {  // below the low-precision trace noise
-            mu = next;
+        if (err < 0.0) {
+            lo = mu;
+            f_lo = err;
+            if (side == -1) f_hi *= 0.5;
+            side = -1;
+        } else {
+            hi = mu;
+            f_hi = err;
+            if (side == 1) f_lo *= 0.5;
+            side = 1;
+        }
+        const double step = (trdd > 1e-300) ? -err / (beta * trdd) : 0.0;
+        if (trdd > 1e-300 && fabs(step) * beta <= u_stop) {
             converged = true;
             break;
+        }
+        double next = mu + step;
+        if (!(trdd > 1e-300) || !(next > lo && next < hi)) {
+            // regula falsi on the bracket (Illinois-weighted)
+            next = (lo * f_hi - hi * f_lo) / (f_hi - f_lo);
+            if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
         }
         mu = next;
     }
     if (pe != P_F64) {
         if (!opt.fd_final_fp64) {
             // low precision end to end (reported, not gated): promote D
-            const size_t m = (size_t)r->lay.np * r->lay.ld;
             int np = 0;
             rc = affine(1, dm, r->lay.ld, 0, r->x64, 1.0, 0.0, 0, &np);
             if (rc) return rc;
-            (void)m;
             dm = r->x64;
             dm_f32 = 0;
         } else {
@@ -247,24 +310,11 @@ int Ctx::solve_finite_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, d
     }
     stats.mu_evals = evals;
     stats.depth = depth;
-    // first-order canonical correction: D <- (1 + c) D - c D^2,
-    // c = beta dmu, dmu = (n_occ - Tr D) / (beta Tr(D - D^2))
-    if (trdd > 1e-300) {
-        const double dmu = (n_occ - tr) / (beta * trdd);
-        const double c = beta * dmu;
-        const size_t m = (size_t)r->lay.np * r->lay.ld;
-        double *out = nullptr;
-        for (int i = 0; i < 5; ++i)
-            if ((void *)(r->x64 + i * m) != dm) {
-                out = r->x64 + i * m;
-                break;
-            }
-        const double coef[3] = {-c, 1.0 + c, 0.0};
-        rc = product(P_F64, dm, dm, dm, out, coef, nullptr, false, false);
+    if (trdd > 1e-300 && fabs(tr - n_occ) > 0.0) {
+        void *out = nullptr;
+        rc = canonical_correction(dm, tr, trdd, &mu, &out);
         if (rc) return rc;
-        close_phase(1);
         dm = out;
-        mu += dmu;
     }
     stats.mu = mu;
     if (!converged && pe == P_F64) status = FDM_ENOCONV;

@@ -165,6 +165,47 @@ __global__ __launch_bounds__(256) void k_affine(const TI *__restrict__ in, int64
     }
 }
 
+// ---- out = a*X + b*Y + c*I on [0,n)^2 (working matrices), zeros elsewhere --
+template <typename T>
+__global__ __launch_bounds__(256) void k_axpby2(const T *__restrict__ X, const T *__restrict__ Y,
+                                                T *__restrict__ out, int64_t ld, int n, int np,
+                                                double a, double b, double c,
+                                                double *__restrict__ part) {
+    __shared__ double red[2][4];
+    double tr = 0.0, f2 = 0.0;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        const int row = blockIdx.x * 4 + rr;
+        if (row >= np) break;
+        for (int col = threadIdx.x; col < np; col += 256) {
+            const int64_t k = (int64_t)row * ld + col;
+            double v = 0.0;
+            if (row < n && col < n)
+                v = a * (double)X[k] + b * (double)Y[k] + (row == col ? c : 0.0);
+            const T o = (T)v;
+            out[k] = o;
+            const double od = (double)o;
+            f2 += od * od;
+            if (row == col) tr += od;
+        }
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    tr = wave_sum(tr);
+    f2 = wave_sum(f2);
+    if (lane == 0) {
+        red[0][w] = tr;
+        red[1][w] = f2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && part != nullptr) {
+        double *p = part + (size_t)blockIdx.x * 4;
+        p[0] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+        p[1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        p[2] = 0.0;
+        p[3] = 0.0;
+    }
+}
+
 // ---- band energy: sum_ij H_ij D_ij and Tr D -------------------------------
 template <typename TD>
 __global__ __launch_bounds__(256) void k_energy(const double *__restrict__ H, int64_t ldh,
@@ -417,6 +458,20 @@ hipError_t launch_energy(const double *H, int64_t ldh, const double *D, int64_t 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_decide(st, nullptr, partials, nb, D_SUMS, 4, s);
+}
+
+hipError_t launch_axpby2(int f32, const void *X, const void *Y, void *out, int64_t ld, int n,
+                         int np, double a, double b, double c, double *partials, int *nparts,
+                         hipStream_t s) {
+    const int nb = affine_blocks(np);
+    if (nparts) *nparts = nb;
+    if (f32)
+        hipLaunchKernelGGL((k_axpby2<float>), dim3(nb), dim3(256), 0, s, (const float *)X,
+                           (const float *)Y, (float *)out, ld, n, np, a, b, c, partials);
+    else
+        hipLaunchKernelGGL((k_axpby2<double>), dim3(nb), dim3(256), 0, s, (const double *)X,
+                           (const double *)Y, (double *)out, ld, n, np, a, b, c, partials);
+    return hipGetLastError();
 }
 
 hipError_t launch_set_params(DevState *st, double n_occ, double tol, double tau, int max_iter,

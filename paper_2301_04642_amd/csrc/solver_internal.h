@@ -95,6 +95,7 @@ struct Ctx {
                double *E_band);
     int validate_symmetric(const double *Hp, int64_t ldh);
     int solve_zero_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, double *E_band);
+    int canonical_correction(void *dm, double tr, double trdd, double *mu, void **out);
     int solve_finite_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, double *E_band);
     int fermi_operator(const double *Hp, int64_t ldh, double mu, int depth, int prec,
                        void **result, int *result_f32, double *trace, double *trace_dd);

@@ -48,6 +48,8 @@ def test_alone_equals_mix(fdm):
             assert np.array_equal(d, alone[r["id"]][0]), r["id"]
             assert e == alone[r["id"]][1]
             d_ref, e_ref, _, _ = reference(wl)
+            print(f"[report] request {r['id']} n={wl.n} kT={wl.kT} |dE|={abs(e - e_ref):.2e} "
+                  f"queue={times[1] - times[0]:.3f}s run={times[2] - times[1]:.3f}s", flush=True)
             assert abs(e - e_ref) <= 1e-6
             starts.append(times[1])
             finishes.append(times[2])

@@ -25,6 +25,23 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "fp16x3": 2500.0, "bf16x3": 2500.0,
 DTYPE = {"fp64": "f64", "fp32": "f32+f64", "fp16x3": "f16x3+f64", "bf16x3": "bf16x3+f64"}
 
 
+def measured_traffic(prec):
+    """HBM bytes per launch of the product kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    try:
+        src = open(os.path.join(ROOT, "paper_2301_04642_amd", "csrc", "k_symprod.hip"), "rb").read()
+        sha = hashlib.sha256(src).hexdigest()[:16]
+        text = open(os.path.join(ROOT, "profiles", "k_symprod_bands_n4000_traffic.md")).read()
+        rec = json.loads(text.split("machine-readable: ", 1)[1].splitlines()[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("source_sha256_16") != sha:
+        return None
+    return rec.get("traffic_bytes_per_launch", {}).get(prec)
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -178,7 +195,7 @@ def main():
         "fp64_solves_per_s": round(res["fp64"]["solves_per_s"], 4),
         "roofline": {"bound": "mfma", "kernel": f"k_symprod<{name_dom}>",
                      "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "frac": round(achieved / peak, 4), "traffic": measured_traffic(name_dom),
                      "avg_launch_ms": round(avg_ms, 4),
                      "flops_per_launch": mult * per_product_flops},
         "forms": forms_out,

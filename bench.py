@@ -46,10 +46,18 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def time_form(fdm, torch, H, wl, prec, steps, warmup, e_ref, timing):
+def parse_form(form):
+    """'fp32' -> ('fp32', 0); 'fp32+lanczos' -> ('fp32', 1)."""
+    prec, _, bnd = form.partition("+")
+    return prec, (1 if bnd == "lanczos" else 0)
+
+
+def time_form(fdm, torch, H, wl, form, steps, warmup, e_ref, timing):
+    prec, bounds = parse_form(form)
     D = torch.empty_like(H)
     opt = fdm.fdm_options_default()
     opt.precision = fdm.PRECISIONS[prec]
+    opt.bounds = bounds
     opt.timing = 1 if timing else 0
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
@@ -73,7 +81,7 @@ def time_form(fdm, torch, H, wl, prec, steps, warmup, e_ref, timing):
         last = st
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return dict(prec=prec, seconds=dt, solves_per_s=steps / dt, ms_per_solve=1e3 * dt / steps,
+    return dict(prec=prec, bounds=bounds, seconds=dt, solves_per_s=steps / dt, ms_per_solve=1e3 * dt / steps,
                 worst_dE=worst_de, worst_idem=worst_idem, stats=last, prod_ms=agg_ms,
                 prod_n=agg_n, prod_flops=agg_flops)
 
@@ -107,9 +115,12 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16x3", "bf16x3"])
+    ap.add_argument("--bounds", default="gershgorin", choices=["gershgorin", "lanczos"],
+                    help="spectral bounds of the headline form and of its fp64 reference")
     ap.add_argument("--n", type=int, default=None, help="override N (testing only)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--forms", default="fp64,fp32,fp16x3,bf16x3")
+    ap.add_argument("--forms", default="fp64,fp32,fp16x3,bf16x3,fp64+lanczos,fp32+lanczos,"
+                                       "fp16x3+lanczos")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -138,20 +149,21 @@ def main():
     wl = workloads.config_workload(1, n=args.n)
     e_ref = float(np.sort(wl.lam)[: int(wl.n_occ)].sum())   # sum of the n_occ lowest
     H = torch.from_numpy(wl.hp).cuda()
+    suffix = "+lanczos" if args.bounds == "lanczos" else ""
+    head_form, ref_form = args.precision + suffix, "fp64" + suffix
     forms = [f for f in args.forms.split(",") if f]
-    if args.precision not in forms:
-        forms.append(args.precision)
-    if "fp64" not in forms:
-        forms.insert(0, "fp64")
+    for f in (ref_form, head_form):
+        if f not in forms:
+            forms.append(f)
     res = {}
-    for prec in forms:
-        log("timing", prec)
-        res[prec] = time_form(fdm, torch, H, wl, prec, args.steps, args.warmup, e_ref, True)
-        r = res[prec]
-        log(f"{prec}: {r['solves_per_s']:.2f} solves/s  {r['ms_per_solve']:.2f} ms  "
+    for form in forms:
+        log("timing", form)
+        res[form] = time_form(fdm, torch, H, wl, form, args.steps, args.warmup, e_ref, True)
+        r = res[form]
+        log(f"{form}: {r['solves_per_s']:.2f} solves/s  {r['ms_per_solve']:.2f} ms  "
             f"|dE|={r['worst_dE']:.2e} idem={r['worst_idem']:.2e}")
 
-    head = res[args.precision]
+    head = res[head_form]
     n = wl.n
     per_product_flops = float(n) * n * (n + 1)   # upper-triangle symmetric product
     # dominant kernel of the headline form: the product class with most time
@@ -162,11 +174,11 @@ def main():
     achieved = mult * per_product_flops / (avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[name_dom]
     forms_out = {}
-    for prec, r in res.items():
+    for form, r in res.items():
         st = r["stats"]
         tot_ms = sum(r["prod_ms"])
         tot_fl = sum(r["prod_flops"])
-        forms_out[prec] = dict(
+        forms_out[form] = dict(
             solves_per_s=round(r["solves_per_s"], 4), ms_per_solve=round(r["ms_per_solve"], 3),
             worst_abs_dE_Ha=r["worst_dE"], worst_idempotency=r["worst_idem"],
             iterations=dict(fp64_first=st.iters_fp64_first, low=st.iters_low,
@@ -175,6 +187,7 @@ def main():
                       if st.products[p]},
             product_tflops=round(tot_fl / (tot_ms * 1e-3) / 1e12, 3) if tot_ms else None,
             product_time_fraction=round(tot_ms / (r["seconds"] * 1e3), 3),
+            bounds=[round(st.e_min, 4), round(st.e_max, 4)],
             gate_pass=bool(r["worst_dE"] <= 1e-6 and r["worst_idem"] <= 1e-8))
     out = {
         "metric": "DM solves/s + X^2 GEMM TFLOP/s, mixed vs FP64 SP2, at |dE_band|<=1e-6 Ha",
@@ -190,9 +203,10 @@ def main():
         "dtype": DTYPE.get(args.precision, args.precision),
         "data": "synthetic",
         "config": {"workload": f"bands-n{n}-nocc{int(wl.n_occ)}-gap0.02-tol1e-8",
-                   "precision": args.precision, "n": n, "n_occ": int(wl.n_occ), "tol": wl.tol},
-        "speedup_vs_fp64": round(head["solves_per_s"] / res["fp64"]["solves_per_s"], 3),
-        "fp64_solves_per_s": round(res["fp64"]["solves_per_s"], 4),
+                   "precision": args.precision, "bounds": args.bounds, "n": n,
+                   "n_occ": int(wl.n_occ), "tol": wl.tol},
+        "speedup_vs_fp64": round(head["solves_per_s"] / res[ref_form]["solves_per_s"], 3),
+        "fp64_solves_per_s": round(res[ref_form]["solves_per_s"], 4),
         "roofline": {"bound": "mfma", "kernel": f"k_symprod<{name_dom}>",
                      "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": measured_traffic(name_dom),
@@ -201,7 +215,7 @@ def main():
         "forms": forms_out,
     }
     if not args.no_cpu:
-        it = res["fp64"]["stats"].iters_fp64 + 1
+        it = res[ref_form]["stats"].iters_fp64 + 1
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(wl, it)
     print(json.dumps(out))

@@ -75,6 +75,11 @@ typedef struct fdm_options {
     int32_t validate;       /* 1: reject an Hp that is not symmetric to 1e-12 relative (0)     */
     int32_t timing;         /* 1: time every product launch with HIP events (0)                */
     int32_t tile;           /* product tile edge: 0 = automatic, or 64 / 128                   */
+    int32_t bounds;         /* spectral bounds: 0 = Gershgorin discs (default); 1 = Gershgorin
+                               tightened by a Lanczos estimate of the extreme eigenvalues
+                               (Ritz values widened by their residual bounds and 1% of the
+                               width, never outside the Gershgorin interval)                  */
+    int32_t lanczos_steps;  /* Lanczos steps for bounds = 1 (default 32, at most 64)           */
     int32_t reserved;
     void *workspace;        /* optional caller-owned device memory of workspace_bytes          */
     size_t workspace_bytes; /* at least fdm_workspace_bytes(N, kT, precision)                  */
@@ -92,7 +97,7 @@ typedef struct fdm_stats {
     int32_t tile;               /* product tile edge used                                       */
     int32_t products[FDM_NPREC];    /* product launches that ran, per precision                */
     uint64_t branch_bits[4];    /* SP2 branch of product k (bit k; 1 = X^2), k < 256           */
-    double e_min, e_max;        /* Gershgorin bounds of Hp                                      */
+    double e_min, e_max;        /* spectral bounds of Hp used by the expansion                  */
     double mu;                  /* finite T: chemical potential of D                           */
     double idempotency;         /* zero T: ||D^2 - D||_F as measured by the last product       */
     double trace;               /* Tr D                                                         */
@@ -101,6 +106,9 @@ typedef struct fdm_stats {
     double prod_ms[FDM_NPREC];  /* summed duration of product launches (timing = 1)            */
     double flops[FDM_NPREC];    /* algorithmic flops of the products that ran: N^2 (N+1) each
                                    (3x for the split forms, which run three products)          */
+    double gersh_min, gersh_max;    /* Gershgorin bounds (e_min / e_max hold the bounds used)  */
+    int32_t lanczos_steps;      /* Lanczos steps run for the bounds (0 with bounds = 0)        */
+    int32_t reserved;
 } fdm_stats;
 
 /* Fills *opt with the defaults listed above.  Returns FDM_EINVAL if opt is NULL. */

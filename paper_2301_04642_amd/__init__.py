@@ -36,6 +36,7 @@ class fdm_options(ctypes.Structure):
                 ("max_mu_evals", ctypes.c_int32), ("fd_extra_depth", ctypes.c_int32),
                 ("fd_final_fp64", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("bounds", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t)]
 
@@ -49,7 +50,9 @@ class fdm_stats(ctypes.Structure):
                 ("e_min", ctypes.c_double), ("e_max", ctypes.c_double), ("mu", ctypes.c_double),
                 ("idempotency", ctypes.c_double), ("trace", ctypes.c_double),
                 ("band_energy", ctypes.c_double), ("ms_total", ctypes.c_double),
-                ("prod_ms", ctypes.c_double * FDM_NPREC), ("flops", ctypes.c_double * FDM_NPREC)]
+                ("prod_ms", ctypes.c_double * FDM_NPREC), ("flops", ctypes.c_double * FDM_NPREC),
+                ("gersh_min", ctypes.c_double), ("gersh_max", ctypes.c_double),
+                ("lanczos_steps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         d = {}

@@ -108,6 +108,10 @@ hipError_t launch_axpby2(int f32, const void *X, const void *Y, void *out, int64
                          int np, double a, double b, double c, double *partials, int *nparts,
                          hipStream_t s);
 
+hipError_t launch_lanczos(const double *H, int64_t ldh, int n, int np, int k, double *v,
+                          double *ab, hipStream_t s);
+hipError_t launch_set_bounds(DevState *st, double emin, double emax, hipStream_t s);
+
 hipError_t launch_set_params(DevState *st, double n_occ, double tol, double tau, int max_iter,
                              int switch_mode, int reset_all, hipStream_t s);
 

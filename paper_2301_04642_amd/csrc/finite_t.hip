@@ -232,6 +232,10 @@ int Ctx::solve_finite_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, d
     DevState h;
     int rc = bounds(Hp, ldh, &h);
     if (rc) return rc;
+    if (opt.bounds == 1 && h.emax > h.emin) {
+        rc = refine_bounds(Hp, ldh, &h);
+        if (rc) return rc;
+    }
     const double beta = 1.0 / kT;
     const int extra = opt.fd_extra_depth;
     const int pe = opt.precision;  // precision of the mu search

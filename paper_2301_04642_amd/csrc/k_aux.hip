@@ -206,6 +206,90 @@ __global__ __launch_bounds__(256) void k_axpby2(const T *__restrict__ X, const T
     }
 }
 
+// ---- Lanczos (tighter spectral bounds) -------------------------------------
+// v_0: deterministic pseudo-random unit vector (single block).
+__global__ __launch_bounds__(1024) void k_lanczos_start(double *__restrict__ v, int n) {
+    __shared__ double red[1024];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) {
+        uint32_t h = (uint32_t)i * 2654435761u + 0x9e3779b9u;
+        h ^= h >> 15;
+        h *= 2246822519u;
+        h ^= h >> 13;
+        const double x = ((double)(h >> 8) + 0.5) / 16777216.0 - 0.5;
+        v[i] = x;
+        s += x * x;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 512; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    const double inv = 1.0 / sqrt(red[0]);
+    for (int i = threadIdx.x; i < n; i += 1024) v[i] *= inv;
+}
+
+// w = H v - beta_prev v_prev, one wave per row of the caller's H.
+__global__ __launch_bounds__(256) void k_lanczos_matvec(const double *__restrict__ H, int64_t ldh,
+                                                        int n, const double *__restrict__ v,
+                                                        const double *__restrict__ vprev,
+                                                        const double *beta_prev,
+                                                        double *__restrict__ w) {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + wv;
+    if (row >= n) return;
+    const double *h = H + (int64_t)row * ldh;
+    double s = 0.0;
+    for (int j = lane; j < n; j += 64) s += h[j] * v[j];
+    s = wave_sum(s);
+    if (lane == 0) w[row] = s - (beta_prev ? *beta_prev * vprev[row] : 0.0);
+}
+
+// alpha = w.v ; w -= alpha v ; beta = ||w|| ; w <- w / beta (single block,
+// fixed-order reductions).
+__global__ __launch_bounds__(1024) void k_lanczos_update(double *__restrict__ w,
+                                                         const double *__restrict__ v, int n,
+                                                         double *alpha, double *beta) {
+    __shared__ double red[1024];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) s += w[i] * v[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 512; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    const double a = red[0];
+    __syncthreads();
+    s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) {
+        const double x = w[i] - a * v[i];
+        w[i] = x;
+        s += x * x;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 512; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    const double b = sqrt(red[0]);
+    const double inv = b > 0.0 ? 1.0 / b : 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) w[i] *= inv;
+    if (threadIdx.x == 0) {
+        *alpha = a;
+        *beta = b;
+    }
+}
+
+__global__ void k_set_bounds(DevState *st, double emin, double emax) {
+    if (threadIdx.x == 0) {
+        st->emin = emin;
+        st->emax = emax;
+    }
+}
+
 // ---- band energy: sum_ij H_ij D_ij and Tr D -------------------------------
 template <typename TD>
 __global__ __launch_bounds__(256) void k_energy(const double *__restrict__ H, int64_t ldh,
@@ -471,6 +555,29 @@ hipError_t launch_axpby2(int f32, const void *X, const void *Y, void *out, int64
     else
         hipLaunchKernelGGL((k_axpby2<double>), dim3(nb), dim3(256), 0, s, (const double *)X,
                            (const double *)Y, (double *)out, ld, n, np, a, b, c, partials);
+    return hipGetLastError();
+}
+
+// k Lanczos steps on the caller's H: v holds 3 vectors of stride np; ab
+// receives alpha[0..k) then beta[0..k).
+hipError_t launch_lanczos(const double *H, int64_t ldh, int n, int np, int k, double *v,
+                          double *ab, hipStream_t s) {
+    hipLaunchKernelGGL(k_lanczos_start, dim3(1), dim3(1024), 0, s, v, n);
+    const int nb = (n + 3) / 4;
+    for (int j = 0; j < k; ++j) {
+        double *vj = v + (size_t)(j % 3) * np;
+        double *vp = v + (size_t)((j + 2) % 3) * np;
+        double *vn = v + (size_t)((j + 1) % 3) * np;
+        hipLaunchKernelGGL(k_lanczos_matvec, dim3(nb), dim3(256), 0, s, H, ldh, n, vj, vp,
+                           j ? ab + k + j - 1 : (const double *)nullptr, vn);
+        hipLaunchKernelGGL(k_lanczos_update, dim3(1), dim3(1024), 0, s, vn, vj, n, ab + j,
+                           ab + k + j);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_set_bounds(DevState *st, double emin, double emax, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_bounds, dim3(1), dim3(64), 0, s, st, emin, emax);
     return hipGetLastError();
 }
 

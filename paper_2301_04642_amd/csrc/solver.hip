@@ -84,6 +84,8 @@ Layout plan_layout(int64_t n, bool finite, int prec) {
     off += round_up(tiles64 * 4, 256);
     L.off_tiles128 = off;
     off += round_up(tiles128 * 4, 256);
+    L.off_lanczos = off;
+    off += round_up((3 * L.np + 2 * kMaxLanczos) * sizeof(double), 256);
     L.off_state = off;
     off += round_up(sizeof(DevState), 256);
     L.bytes = off;
@@ -158,6 +160,7 @@ int Resources::bind(const Layout &L, void *user_mem, size_t user_bytes, hipStrea
     tiles64 = (uint32_t *)(mem + L.off_tiles64);
     tiles128 = (uint32_t *)(mem + L.off_tiles128);
     st = (DevState *)(mem + L.off_state);
+    lanczos = (double *)(mem + L.off_lanczos);
     if (fresh) {
         // zero every matrix (the padding must hold zeros) and upload tile lists
         e = hipMemsetAsync(mem, 0, L.off_part, s);
@@ -423,13 +426,108 @@ int Ctx::bounds(const double *Hp, int64_t ldh, DevState *h) {
     if (e != hipSuccess) return hip_fail(e, "gershgorin launch");
     int rc = read_state(h);
     if (rc) return rc;
-    stats.e_min = h->emin;
-    stats.e_max = h->emax;
+    stats.e_min = stats.gersh_min = h->emin;
+    stats.e_max = stats.gersh_max = h->emax;
     if (h->nonfinite) {
         set_error("Hp holds NaN or Inf in " + std::to_string(h->nonfinite) + " rows");
         return FDM_ENONFINITE;
     }
     return FDM_OK;
+}
+
+// Eigenpairs of a small dense symmetric matrix (cyclic Jacobi), for the
+// Lanczos tridiagonal.  a is k x k row-major (destroyed); w, V (columns).
+static void small_eigh(int k, std::vector<double> &a, std::vector<double> &w,
+                       std::vector<double> &V) {
+    V.assign((size_t)k * k, 0.0);
+    for (int i = 0; i < k; ++i) V[(size_t)i * k + i] = 1.0;
+    for (int sweep = 0; sweep < 80; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < k; ++j) {
+                const double x = a[(size_t)i * k + j];
+                tot += x * x;
+                if (i != j) off += x * x;
+            }
+        if (off <= 1e-30 * tot || off == 0.0) break;
+        for (int p = 0; p < k - 1; ++p)
+            for (int q = p + 1; q < k; ++q) {
+                const double apq = a[(size_t)p * k + q];
+                if (apq == 0.0) continue;
+                const double th = (a[(size_t)q * k + q] - a[(size_t)p * k + p]) / (2.0 * apq);
+                const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+                const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
+                for (int r = 0; r < k; ++r) {
+                    const double x = a[(size_t)r * k + p], y = a[(size_t)r * k + q];
+                    a[(size_t)r * k + p] = c * x - sn * y;
+                    a[(size_t)r * k + q] = sn * x + c * y;
+                }
+                for (int r = 0; r < k; ++r) {
+                    const double x = a[(size_t)p * k + r], y = a[(size_t)q * k + r];
+                    a[(size_t)p * k + r] = c * x - sn * y;
+                    a[(size_t)q * k + r] = sn * x + c * y;
+                }
+                for (int r = 0; r < k; ++r) {
+                    const double x = V[(size_t)r * k + p], y = V[(size_t)r * k + q];
+                    V[(size_t)r * k + p] = c * x - sn * y;
+                    V[(size_t)r * k + q] = sn * x + c * y;
+                }
+            }
+    }
+    w.resize(k);
+    for (int i = 0; i < k; ++i) w[i] = a[(size_t)i * k + i];
+}
+
+// Tighter bounds: k Lanczos steps on Hp give the tridiagonal T_k; its extreme
+// eigenvalues theta are Ritz values of Hp with residual |beta_k s_k| (s_k the
+// last component of T_k's eigenvector).  The bounds are theta -+ (residual +
+// 1% of the Ritz width), clipped to the Gershgorin interval in *h.
+int Ctx::refine_bounds(const double *Hp, int64_t ldh, DevState *h) {
+    int k = opt.lanczos_steps > 0 ? std::min(opt.lanczos_steps, kMaxLanczos) : 32;
+    k = (int)std::min<int64_t>(k, n);
+    if (k < 2) return FDM_OK;
+    double *ab = r->lanczos + 3 * r->lay.np;
+    hipError_t e = launch_lanczos(Hp, ldh, (int)n, (int)r->lay.np, k, r->lanczos, ab, s);
+    if (e != hipSuccess) return hip_fail(e, "lanczos launch");
+    std::vector<double> hab(2 * k);
+    e = hipMemcpyAsync(hab.data(), ab, 2 * k * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    const double *alpha = hab.data(), *beta = hab.data() + k;
+    double scale = 0.0;
+    for (int j = 0; j < k; ++j) scale = std::max(scale, fabs(alpha[j]) + fabs(beta[j]));
+    int m = k;  // an (almost) invariant Krylov space ends the recursion early
+    for (int j = 0; j < k - 1; ++j)
+        if (!(beta[j] > 1e-13 * scale)) {
+            m = j + 1;
+            break;
+        }
+    std::vector<double> T((size_t)m * m, 0.0), w, V;
+    for (int j = 0; j < m; ++j) {
+        T[(size_t)j * m + j] = alpha[j];
+        if (j + 1 < m) T[(size_t)j * m + j + 1] = T[(size_t)(j + 1) * m + j] = beta[j];
+    }
+    small_eigh(m, T, w, V);
+    int imin = 0, imax = 0;
+    for (int i = 1; i < m; ++i) {
+        if (w[i] < w[imin]) imin = i;
+        if (w[i] > w[imax]) imax = i;
+    }
+    const double bk = (m == k) ? beta[k - 1] : 0.0;
+    const double rmin = fabs(bk * V[(size_t)(m - 1) * m + imin]);
+    const double rmax = fabs(bk * V[(size_t)(m - 1) * m + imax]);
+    const double margin = 0.01 * (w[imax] - w[imin]) + 1e-12 * scale;
+    const double lo = std::max(h->emin, w[imin] - rmin - margin);
+    const double hi = std::min(h->emax, w[imax] + rmax + margin);
+    if (!(hi > lo)) return FDM_OK;  // keep the Gershgorin interval
+    h->emin = lo;
+    h->emax = hi;
+    stats.e_min = lo;
+    stats.e_max = hi;
+    stats.lanczos_steps = m;
+    e = launch_set_bounds(r->st, lo, hi, s);
+    return e == hipSuccess ? FDM_OK : hip_fail(e, "set_bounds launch");
 }
 
 int Ctx::solve_zero_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, double *E_band) {
@@ -453,6 +551,10 @@ int Ctx::solve_zero_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, dou
     if (!(h.emax > h.emin)) {
         set_error("Hp is a multiple of the identity: no gap at n_occ");
         return FDM_ENOCONV;
+    }
+    if (opt.bounds == 1) {
+        rc = refine_bounds(Hp, ldh, &h);
+        if (rc) return rc;
     }
     const int prec = opt.precision;
     const int max_iter = opt.max_iter;
@@ -492,9 +594,9 @@ int Ctx::solve_zero_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, dou
         k64 = ratio > 1.0 ? (int)ceil(log2(ratio)) : 0;
         // Larger N puts more states next to the gap and larger accumulation
         // errors into each product; measured on MI355X with FP32 bulk
-        // products: N = 4000 passes |dE| <= 1e-6 with 5 FP64 steps (5.8e-8),
-        // N = 30000 needs 20 (4.8e-7; 16 gives 7.9e-6).
-        if (n > 4000) k64 += 5 * (int)ceil(log2((double)n / 4000.0));
+        // products and Gershgorin bounds: N = 4000 passes |dE| <= 1e-6 with 5
+        // FP64 steps (5.8e-8), N = 30000 needs 20 (4.8e-7; 16 gives 7.9e-6).
+        if (n > 4000) k64 += (opt.bounds == 1 ? 1 : 5) * (int)ceil(log2((double)n / 4000.0));
         k64 = std::min(std::max(k64, 0), 24);
     }
     double tau = opt.tau;
@@ -576,6 +678,8 @@ int fdm_options_default(fdm_options *opt) {
     opt->validate = 0;
     opt->timing = 0;
     opt->tile = 0;
+    opt->bounds = 0;
+    opt->lanczos_steps = 32;
     return FDM_OK;
 }
 
@@ -611,7 +715,8 @@ int fermi_dm_solve(const double *Hp, int64_t N, int64_t ldh, double n_occ, doubl
         fdm_options_default(&opt);
     if (!Hp || !D || N <= 0 || N >= 65535 * 64 || ldh < N || ldd < N || !(tol > 0.0) ||
         !(kT >= 0.0) || !std::isfinite(kT) || opt.precision < 0 || opt.precision >= FDM_NPREC ||
-        opt.max_iter <= 0 || (opt.tile != 0 && opt.tile != 64 && opt.tile != 128)) {
+        opt.max_iter <= 0 || (opt.tile != 0 && opt.tile != 64 && opt.tile != 128) ||
+        opt.bounds < 0 || opt.bounds > 1) {
         set_error("invalid argument");
         return FDM_EINVAL;
     }

@@ -11,6 +11,8 @@
 
 namespace fdm {
 
+constexpr int kMaxLanczos = 64;
+
 // Carving of one workspace allocation: n64 FP64 and n32 FP32 zero-padded
 // np x ld working matrices, per-tile partial sums, two tile lists and the
 // device state.
@@ -18,6 +20,7 @@ struct Layout {
     int64_t n = 0, np = 0, ld = 0;
     int n64 = 0, n32 = 0;
     size_t off64 = 0, off32 = 0, off_part = 0, off_tiles64 = 0, off_tiles128 = 0, off_state = 0;
+    size_t off_lanczos = 0;  // 3 vectors of np doubles + alpha/beta (2 x kMaxLanczos)
     size_t bytes = 0;
     int ntiles64 = 0, ntiles128 = 0;
     int64_t part_cap = 0;
@@ -38,6 +41,7 @@ struct Resources {
     float *x32 = nullptr;
     double *part = nullptr;
     uint32_t *tiles64 = nullptr, *tiles128 = nullptr;
+    double *lanczos = nullptr;
     DevState *st = nullptr;
     HostMirror *hm_host = nullptr, *hm_dev = nullptr;
     DevState *st_pinned = nullptr;
@@ -91,6 +95,7 @@ struct Ctx {
                       int *steps);
     int read_state(DevState *out);
     int bounds(const double *Hp, int64_t ldh, DevState *h);
+    int refine_bounds(const double *Hp, int64_t ldh, DevState *h);
     int finish(const double *Hp, int64_t ldh, const void *dm, int dm_f32, double *D, int64_t ldd,
                double *E_band);
     int validate_symmetric(const double *Hp, int64_t ldh);

@@ -33,21 +33,27 @@ def sampled_checks(wl, d, f, rows, tol_rows, tol_idem, tol_comm):
     assert comm <= tol_comm
 
 
-def test_config3_n30000_fp32_mixed(fdm):
+@pytest.fixture(scope="module")
+def config3():
+    say("generate config3 N=30000")
+    return workloads.config_workload(3)
+
+
+@pytest.mark.parametrize("prec,bounds", [("fp32", 0), ("fp32", 1), ("fp16x3", 1)])
+def test_config3_n30000_mixed(fdm, config3, prec, bounds):
     """N = 30000, n_occ = 7500, bands + 1% outliers up to 5 Ha, gap 0.05 Ha:
     FP32 bulk with FP64 first steps, traces and McWeeny refinement."""
     from oracle import density as den
-    say("generate config3 N=30000")
-    wl = workloads.config_workload(3)
+    wl = config3
     H = dev(wl.hp)
-    say("solve config3 fp32")
-    D, e, st = fdm.solve(H, wl.n_occ, 0.0, 1e-8, "fp32")
+    say("solve config3", prec, "bounds", bounds)
+    D, e, st = fdm.solve(H, wl.n_occ, 0.0, 1e-8, prec, bounds=bounds)
     del H
     d = host(D)
     del D
     f, _ = den.occupations(wl.lam, wl.n_occ, 0.0)
     e_ref = float(np.dot(f, wl.lam))
-    print(f"[report] config3: k64={st.iters_fp64_first} low={st.iters_low} mcw={st.mcweeny_steps} "
+    print(f"[report] config3 {prec} bounds={bounds}: k64={st.iters_fp64_first} low={st.iters_low} mcw={st.mcweeny_steps} "
           f"|dE|={abs(e - e_ref):.2e} idem={st.idempotency:.2e} bounds=({st.e_min:.1f},{st.e_max:.1f})",
           flush=True)
     assert st.status == 0

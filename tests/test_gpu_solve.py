@@ -23,7 +23,7 @@ def check_fp64(fdm, wl, tol=1e-11, **opts):
     from oracle import density as den
     from oracle import sp2
     d_ref, e_ref, _, _ = reference(wl)
-    say("solve fp64", wl.name, wl.n)
+    say("solve fp64", wl.name, wl.n, opts)
     D, e, st = fdm.solve(dev(wl.hp), wl.n_occ, 0.0, tol, "fp64", **opts)
     d = host(D)
     assert st.status == 0
@@ -34,11 +34,13 @@ def check_fp64(fdm, wl, tol=1e-11, **opts):
     assert np.linalg.norm(wl.hp @ d - d @ wl.hp) <= 1e-10
     assert np.array_equal(d, d.T)
     assert abs(den.band_energy(wl.hp, d) - e) <= 1e-10
-    # the oracle SP2 takes the same branches (no decision is near a tie here)
-    _, info = sp2.sp2(wl.hp, wl.n_occ, tol=tol)
+    # the oracle SP2 takes the same branches (no decision is near a tie here);
+    # with tightened bounds the oracle is given the bounds the GPU used
+    bounds = None if opts.get("bounds", 0) == 0 else (st.e_min, st.e_max)
+    _, info = sp2.sp2(wl.hp, wl.n_occ, tol=tol, bounds=bounds)
     assert fdm.branch_list(st) == info["branches"][:256]
     assert st.iters_fp64 == info["iterations"]
-    assert abs(st.e_min - info["bounds"][0]) < 1e-12 * abs(info["bounds"][0])
+    assert abs(st.gersh_min - sp2.gershgorin_bounds(wl.hp)[0]) < 1e-12 * abs(st.gersh_min)
     return st
 
 
@@ -51,6 +53,24 @@ def test_config0_fp64(fdm):
 @pytest.mark.parametrize("n", [2, 7, 63, 64, 65, 127, 129, 300])
 def test_ragged_sizes_fp64(fdm, n):
     check_fp64(fdm, workloads.config_workload(0, n=n))
+
+
+@pytest.mark.parametrize("cfg,n", [(0, 256), (1, 1000), (3, 1200), (0, 9)])
+def test_lanczos_bounds(fdm, cfg, n):
+    """Tightened bounds bracket the exact spectrum, stay inside Gershgorin,
+    are within 5% of the spectral width, and cut the SP2 product count."""
+    wl = workloads.config_workload(cfg, n=n)
+    lam = np.sort(wl.lam)
+    st_g = check_fp64(fdm, wl)
+    st = check_fp64(fdm, wl, bounds=1)
+    width = lam[-1] - lam[0]
+    print(f"[report] bounds n={n}: lanczos [{st.e_min:.4f}, {st.e_max:.4f}] "
+          f"exact [{lam[0]:.4f}, {lam[-1]:.4f}] gershgorin [{st.gersh_min:.2f}, {st.gersh_max:.2f}] "
+          f"steps {st.lanczos_steps} products {st_g.iters_fp64} -> {st.iters_fp64}", flush=True)
+    assert st.e_min <= lam[0] and st.e_max >= lam[-1]
+    assert st.e_min >= lam[0] - 0.05 * width and st.e_max <= lam[-1] + 0.05 * width
+    assert st.gersh_min <= st.e_min and st.e_max <= st.gersh_max
+    assert st.iters_fp64 <= st_g.iters_fp64
 
 
 @pytest.mark.parametrize("tile", [64, 128])
@@ -155,6 +175,11 @@ def test_mixed_bands_small(fdm, prec):
 
 
 @pytest.mark.parametrize("prec", MIXED)
+def test_mixed_bands_lanczos(fdm, prec):
+    check_mixed(fdm, workloads.config_workload(1, n=1000), prec, bounds=1)
+
+
+@pytest.mark.parametrize("prec", MIXED)
 def test_mixed_k64_zero(fdm, prec):
     """Low precision from the first step (no FP64-first phase)."""
     st, _ = check_mixed(fdm, workloads.config_workload(0, n=500), prec, k64=0)
@@ -190,3 +215,4 @@ def test_config1_full_size(fdm, config1, prec):
         assert st.idempotency <= 1e-11
     else:
         check_mixed(fdm, config1, prec)
+        check_mixed(fdm, config1, prec, bounds=1)

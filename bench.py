@@ -115,7 +115,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16x3", "bf16x3"])
-    ap.add_argument("--bounds", default="gershgorin", choices=["gershgorin", "lanczos"],
+    ap.add_argument("--bounds", default="lanczos", choices=["gershgorin", "lanczos"],
                     help="spectral bounds of the headline form and of its fp64 reference")
     ap.add_argument("--n", type=int, default=None, help="override N (testing only)")
     ap.add_argument("--no-cpu", action="store_true")

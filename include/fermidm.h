@@ -75,7 +75,7 @@ typedef struct fdm_options {
     int32_t validate;       /* 1: reject an Hp that is not symmetric to 1e-12 relative (0)     */
     int32_t timing;         /* 1: time every product launch with HIP events (0)                */
     int32_t tile;           /* product tile edge: 0 = automatic, or 64 / 128                   */
-    int32_t bounds;         /* spectral bounds: 0 = Gershgorin discs (default); 1 = Gershgorin
+    int32_t bounds;         /* spectral bounds: 0 = Gershgorin discs; 1 (default) = Gershgorin
                                tightened by a Lanczos estimate of the extreme eigenvalues
                                (Ritz values widened by their residual bounds and 1% of the
                                width, never outside the Gershgorin interval)                  */
@@ -127,7 +127,8 @@ size_t fdm_workspace_bytes(int64_t N, double kT, int32_t precision);
  *         kT >  0: the electron count Tr D, real in (0, N).
  *  kT     electronic temperature in Hartree (k_B T_e; beta = 1/kT).  0 selects
  *         the zero-temperature projector.
- *  tol    kT == 0: stop when ||X^2 - X||_F <= tol;  kT > 0: stop the mu
+ *  tol    kT == 0: stop when ||X^2 - X||_F <= tol and |Tr X - n_occ| <= tol;
+ *         kT > 0: stop the mu
  *         search when |Tr D - n_occ| <= tol or the Newton step in mu is below
  *         1e-3 kT (a second-order correction of D in mu follows).  Must be > 0.
  *  D      device, N x N, leading dimension ldd >= N: receives D (full,

@@ -400,7 +400,9 @@ __global__ __launch_bounds__(256) void k_decide(DevState *st, HostMirror *hm,
             // iteration sits on its rounding floor.
             const bool stagnant = idem < 0.1 && idem >= 0.8 * two_back;
             const bool advance_bit = true;
-            if (idem <= st->tol) {
+            // converged: idempotent and holding n_occ electrons (st->trace is
+            // still Tr X_n here)
+            if (idem <= st->tol && fabs(st->trace - st->n_occ) <= st->tol) {
                 st->done = 1;
                 st->result_iter = n;
                 break;
@@ -432,7 +434,7 @@ __global__ __launch_bounds__(256) void k_decide(DevState *st, HostMirror *hm,
             const double idem = sqrt(s2);
             st->idem = idem;
             st->executed += 1;
-            if (idem <= st->tol) {
+            if (idem <= st->tol && fabs(st->trace - st->n_occ) <= st->tol) {
                 st->done = 1;
                 st->result_iter = st->iter;
             } else if (st->iter >= st->max_iter) {

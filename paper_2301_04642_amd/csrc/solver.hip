@@ -612,7 +612,7 @@ int Ctx::solve_zero_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, dou
         rc = sp2_phase(P_F64, X64[0], X64[1], k64, 2, tau, &res, &it);
         if (rc) return rc;
         stats.iters_fp64_first = it;
-        if (r->hm_host->idem <= tol && r->hm_host->result_iter < k64) {
+        if (r->hm_host->done && r->hm_host->result_iter < k64 && r->hm_host->idem <= tol) {
             stats.idempotency = r->hm_host->idem;
             return finish(Hp, ldh, res, 0, D, ldd, E_band);
         }
@@ -678,7 +678,7 @@ int fdm_options_default(fdm_options *opt) {
     opt->validate = 0;
     opt->timing = 0;
     opt->tile = 0;
-    opt->bounds = 0;
+    opt->bounds = 1;
     opt->lanczos_steps = 32;
     return FDM_OK;
 }

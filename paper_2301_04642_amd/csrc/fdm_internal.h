@@ -74,6 +74,11 @@ struct ProdArgs {
     const int32_t *sel;
     const int32_t *done;    // nullable: exit at once if *done != 0
     double *partials;       // [ntiles][4]
+    // Split forms: hi/lo 16-bit companions of A, B (read as operands) and C
+    // (written by the epilogue); lo = hi + hl_off elements.
+    const uint16_t *Ahl, *Bhl;
+    uint16_t *Chl;
+    int64_t hl_off;
 };
 
 // ---- launchers (k_symprod.hip, k_aux.hip) --------------------------------
@@ -111,6 +116,11 @@ hipError_t launch_axpby2(int f32, const void *X, const void *Y, void *out, int64
 hipError_t launch_lanczos(const double *H, int64_t ldh, int n, int np, int k, double *v,
                           double *ab, hipStream_t s);
 hipError_t launch_set_bounds(DevState *st, double emin, double emax, hipStream_t s);
+
+// hi/lo 16-bit companions of an FP32 working matrix (split precisions):
+// hi = rn(s x), lo = rn(s x - hi), s = 2^12 for FP16, 1 for BF16.
+hipError_t launch_split(int prec, const float *x, uint16_t *hl, int64_t hl_off, int64_t count,
+                        hipStream_t s);
 
 hipError_t launch_set_params(DevState *st, double n_occ, double tol, double tau, int max_iter,
                              int switch_mode, int reset_all, hipStream_t s);

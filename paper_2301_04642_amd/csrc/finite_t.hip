@@ -239,6 +239,7 @@ int Ctx::solve_finite_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, d
     const double beta = 1.0 / kT;
     const int extra = opt.fd_extra_depth;
     const int pe = opt.precision;  // precision of the mu search
+    split_prec = pe;
     // start: uniform-density-of-states guess from the exact moments
     const double m1 = h.trH / (double)n;
     const double m2 = std::max(h.fro2H / (double)n - m1 * m1, 0.0);
@@ -348,6 +349,7 @@ extern "C" int fdm_fermi_operator(const double *Hp, int64_t N, int64_t ldh, doub
     memset(&c.stats, 0, sizeof(c.stats));
     c.n = N;
     c.kT = kT;
+    c.split_prec = precision;
     int rc = r->bind(plan_layout(N, true, precision), nullptr, 0, c.s);
     if (rc) return rc;
     DevState h;

@@ -22,8 +22,10 @@
 //    lane / 16).  The k order inside a fragment is irrelevant because A and
 //    B use the same one: FP64 feeds 2 v_mfma_f64_16x16x4 per fragment, FP32
 //    4 v_mfma_f32_16x16x4, FP16/BF16 one v_mfma_f32_16x16x32.
-//  * Split forms keep an FP32 master matrix and split it while staging:
-//    hi = round(s*x), lo = round(s*x - hi) (s = 2^12 for FP16, 1 for BF16),
+//  * Split forms keep an FP32 master matrix (epilogue operand, sums) and
+//    16-bit hi/lo companions written once by the producer:
+//    hi = round(s*x), lo = round(s*x - hi) (s = 2^12 for FP16, 1 for BF16);
+//    the operand stages copy the companions straight into LDS and
 //    AB ~ (hi hi + hi lo + lo hi) / s^2 with FP32 accumulation.
 //  * Workgroups go round-robin over the 8 XCDs; the block index is remapped
 //    so each XCD works on a contiguous run of the tile list (shared row
@@ -124,6 +126,34 @@ __device__ __forceinline__ void to_halves(const u4_t &raw, u2_t &hi, u2_t &lo) {
 }
 
 template <int P>
+__device__ __forceinline__ void split1(float x, uint16_t &hi, uint16_t &lo) {
+    if constexpr (PT<P>::F16) {
+        const float s = x * kF16Scale;
+        const _Float16 hh = (_Float16)s;
+        hi = __builtin_bit_cast(uint16_t, hh);
+        lo = __builtin_bit_cast(uint16_t, (_Float16)(s - (float)hh));
+    } else {
+        const __bf16 hh = (__bf16)x;
+        hi = __builtin_bit_cast(uint16_t, hh);
+        lo = __builtin_bit_cast(uint16_t, (__bf16)(x - (float)hh));
+    }
+}
+
+// hi/lo companions of an FP32 working matrix (elementwise, whole padded area)
+template <int P>
+__global__ __launch_bounds__(256) void k_split(const float *__restrict__ x,
+                                               uint16_t *__restrict__ hl, int64_t hl_off,
+                                               int64_t count) {
+    const int64_t i4 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    if (i4 >= count) return;
+    const u4_t raw = *(const u4_t *)(x + i4);
+    u2_t h, l;
+    to_halves<P>(raw, h, l);
+    *(u2_t *)(hl + i4) = h;
+    *(u2_t *)(hl + hl_off + i4) = l;
+}
+
+template <int P>
 __device__ __forceinline__ typename PT<P>::Acc mfma_frag(const u4_t &a, const u4_t &b,
                                                          const u4_t &alo, const u4_t &blo,
                                                          typename PT<P>::Acc c) {
@@ -194,14 +224,23 @@ void k_symprod(ProdArgs a) {
     const S *__restrict__ B = (const S *)a.B;
 
     u4_t ga[NL], gb[NL];
+    const uint16_t *__restrict__ Ahl = a.Ahl;
+    const uint16_t *__restrict__ Bhl = a.Bhl;
     auto gload = [&](int kt) {
         const int64_t k0 = (int64_t)kt * KST;
 #pragma unroll
         for (int u = 0; u < NL; ++u) {
             const int c = tid + 256 * u;
             const int r = c >> 3, ch = c & 7;
-            ga[u] = *(const u4_t *)(A + (row0 + r) * ld + k0 + ch * EPC);
-            gb[u] = *(const u4_t *)(B + (col0 + r) * ld + k0 + ch * EPC);
+            if constexpr (SPLIT) {
+                // 16-byte chunks 0-3 of a row stage are hi halves, 4-7 lo halves
+                const int64_t off = (ch >> 2) * a.hl_off + k0 + (ch & 3) * 8;
+                ga[u] = *(const u4_t *)(Ahl + (row0 + r) * ld + off);
+                gb[u] = *(const u4_t *)(Bhl + (col0 + r) * ld + off);
+            } else {
+                ga[u] = *(const u4_t *)(A + (row0 + r) * ld + k0 + ch * EPC);
+                gb[u] = *(const u4_t *)(B + (col0 + r) * ld + k0 + ch * EPC);
+            }
         }
     };
     auto lstore = [&](int st) {
@@ -214,14 +253,17 @@ void k_symprod(ProdArgs a) {
             if constexpr (!HALF) {
                 *(u4_t *)(pa + r * RSB + ch * 16) = ga[u];
                 *(u4_t *)(pb + r * RSB + ch * 16) = gb[u];
+            } else if constexpr (SPLIT) {
+                const int off = (ch >> 2) * PANEL + r * RSB + (ch & 3) * 16;
+                *(u4_t *)(pa + off) = ga[u];
+                *(u4_t *)(pb + off) = gb[u];
             } else {
+                // single-pass FP16 / BF16: round the FP32 master while staging
                 u2_t h, l;
                 to_halves<P>(ga[u], h, l);
                 *(u2_t *)(pa + r * RSB + ch * 8) = h;
-                if constexpr (SPLIT) *(u2_t *)(pa + PANEL + r * RSB + ch * 8) = l;
                 to_halves<P>(gb[u], h, l);
                 *(u2_t *)(pb + r * RSB + ch * 8) = h;
-                if constexpr (SPLIT) *(u2_t *)(pb + PANEL + r * RSB + ch * 8) = l;
             }
         }
     };
@@ -308,6 +350,16 @@ void k_symprod(ProdArgs a) {
                 if (w != 0.0) {
                     C[row * ld + col] = os;
                     if (diag && row < col) C[col * ld + row] = os;
+                    if constexpr (SPLIT) {
+                        uint16_t h, l;
+                        split1<P>((float)os, h, l);
+                        a.Chl[row * ld + col] = h;
+                        a.Chl[a.hl_off + row * ld + col] = l;
+                        if (diag && row < col) {
+                            a.Chl[col * ld + row] = h;
+                            a.Chl[a.hl_off + col * ld + row] = l;
+                        }
+                    }
                     const double od = (double)os;
                     if (row == col) s_tr += od;
                     s_f2 += w * od * od;
@@ -318,6 +370,15 @@ void k_symprod(ProdArgs a) {
                 if constexpr (ROWS_CONSECUTIVE) {
                     S *dst = C + col * ld + rb + 4 * lg;
                     *(f4_t *)dst = f4_t{(float)ov[0], (float)ov[1], (float)ov[2], (float)ov[3]};
+                    if constexpr (SPLIT) {
+                        u2_t hi4, lo4;
+                        to_halves<P>(bitcast<u4_t>(f4_t{(float)ov[0], (float)ov[1], (float)ov[2],
+                                                        (float)ov[3]}),
+                                     hi4, lo4);
+                        const int64_t m = col * ld + rb + 4 * lg;
+                        *(u2_t *)(a.Chl + m) = hi4;
+                        *(u2_t *)(a.Chl + a.hl_off + m) = lo4;
+                    }
                 } else {
 #pragma unroll
                     for (int q = 0; q < 4; ++q) C[col * ld + rb + lg + 4 * q] = ov[q];
@@ -360,6 +421,21 @@ hipError_t launch_p(int bt, const ProdArgs &a, hipStream_t s) {
 }
 
 }  // namespace
+
+hipError_t launch_split(int prec, const float *x, uint16_t *hl, int64_t hl_off, int64_t count,
+                        hipStream_t s) {
+    if (count % 4) return hipErrorInvalidValue;
+    const int64_t nb = (count / 4 + 255) / 256;
+    if (prec == P_F16X3)
+        hipLaunchKernelGGL((k_split<P_F16X3>), dim3((unsigned)nb), dim3(256), 0, s, x, hl, hl_off,
+                           count);
+    else if (prec == P_BF16X3)
+        hipLaunchKernelGGL((k_split<P_BF16X3>), dim3((unsigned)nb), dim3(256), 0, s, x, hl,
+                           hl_off, count);
+    else
+        return hipSuccess;
+    return hipGetLastError();
+}
 
 hipError_t launch_symprod(int prec, int bt, const ProdArgs &a, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;

@@ -78,6 +78,8 @@ Layout plan_layout(int64_t n, bool finite, int prec) {
     off += mat64 * L.n64;
     L.off32 = off;
     off += mat32 * L.n32;
+    L.off16 = off;
+    off += mat32 * L.n32;  // hi + lo halves per element
     L.off_part = off;
     off += round_up(parts * 8 * sizeof(double), 256);
     L.off_tiles64 = off;
@@ -156,6 +158,7 @@ int Resources::bind(const Layout &L, void *user_mem, size_t user_bytes, hipStrea
     lay = L;
     x64 = (double *)(mem + L.off64);
     x32 = (float *)(mem + L.off32);
+    x16 = (uint16_t *)(mem + L.off16);
     part = (double *)(mem + L.off_part);
     tiles64 = (uint32_t *)(mem + L.off_tiles64);
     tiles128 = (uint32_t *)(mem + L.off_tiles128);
@@ -163,7 +166,7 @@ int Resources::bind(const Layout &L, void *user_mem, size_t user_bytes, hipStrea
     lanczos = (double *)(mem + L.off_lanczos);
     if (fresh) {
         // zero every matrix (the padding must hold zeros) and upload tile lists
-        e = hipMemsetAsync(mem, 0, L.off_part, s);
+        e = hipMemsetAsync(mem, 0, L.off_part, s);  // FP64, FP32 and 16-bit companions
         if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
         e = hipMemsetAsync(st, 0, sizeof(DevState), s);
         if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
@@ -237,6 +240,23 @@ int Ctx::product(int prec, const void *A, const void *B, const void *E, void *C,
     a.sel = sel ? &r->st->sigma : nullptr;
     a.done = done_guard ? &r->st->done : nullptr;
     a.partials = r->part;
+    if (prec == P_F16X3 || prec == P_BF16X3) {
+        const size_t m = (size_t)r->lay.np * r->lay.ld;
+        auto comp = [&](const void *p) -> uint16_t * {
+            const float *f = (const float *)p;
+            if (f < r->x32 || f >= r->x32 + (size_t)r->lay.n32 * m) return nullptr;
+            const size_t i = (size_t)(f - r->x32) / m;
+            return r->x16 + i * 2 * m;
+        };
+        a.Ahl = comp(A);
+        a.Bhl = comp(B);
+        a.Chl = comp(C);
+        a.hl_off = (int64_t)m;
+        if (!a.Ahl || !a.Bhl || !a.Chl) {
+            set_error("internal: split operand outside the FP32 working buffers");
+            return FDM_EHIP;
+        }
+    }
     last_ntiles = a.ntiles;
     used_tile = bt;
     hipError_t e;
@@ -290,7 +310,18 @@ int Ctx::affine(int in_f32, const void *in, int64_t ldi, int out_f32, void *out,
                 double b, int zt, int *nparts) {
     hipError_t e = launch_affine(in_f32, in, ldi, out_f32, out, r->lay.ld, (int)n,
                                  (int)r->lay.np, a, b, zt, r->st, r->part, nparts, s);
-    return e == hipSuccess ? FDM_OK : hip_fail(e, "affine launch");
+    if (e != hipSuccess) return hip_fail(e, "affine launch");
+    if (out_f32 && (split_prec == P_F16X3 || split_prec == P_BF16X3)) {
+        // an FP32 operand of split products: write its hi/lo companions
+        const size_t m = (size_t)r->lay.np * r->lay.ld;
+        const float *f = (const float *)out;
+        if (f >= r->x32 && f < r->x32 + (size_t)r->lay.n32 * m) {
+            const size_t i = (size_t)(f - r->x32) / m;
+            e = launch_split(split_prec, f, r->x16 + i * 2 * m, (int64_t)m, (int64_t)m, s);
+            if (e != hipSuccess) return hip_fail(e, "split launch");
+        }
+    }
+    return FDM_OK;
 }
 
 // Runs `enqueue(k)` for k = 0, 1, ... keeping exactly one step in flight
@@ -581,6 +612,7 @@ int Ctx::solve_zero_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, dou
     }
 
     // ---- mixed forms ----
+    split_prec = prec;
     int k64 = opt.k64;
     if (k64 < 0) {
         // FP64 steps while the Gershgorin over-estimate of the spectral width
@@ -815,6 +847,7 @@ int fdm_sym_product(int32_t precision, const double *A, const double *B, const d
     c.opt.tile = tile;
     c.n = N;
     const bool lo = precision != P_F64;
+    c.split_prec = precision;
     // Operands are packed into zero-padded working matrices of the product's
     // precision (FP64, or the FP32 master of the low-precision forms).
     Layout L = plan_layout(N, true, lo ? P_F32 : P_F64);

@@ -21,6 +21,7 @@ struct Layout {
     int n64 = 0, n32 = 0;
     size_t off64 = 0, off32 = 0, off_part = 0, off_tiles64 = 0, off_tiles128 = 0, off_state = 0;
     size_t off_lanczos = 0;  // 3 vectors of np doubles + alpha/beta (2 x kMaxLanczos)
+    size_t off16 = 0;        // hi/lo 16-bit companions of the FP32 buffers
     size_t bytes = 0;
     int ntiles64 = 0, ntiles128 = 0;
     int64_t part_cap = 0;
@@ -39,6 +40,7 @@ struct Resources {
     Layout lay;
     double *x64 = nullptr;
     float *x32 = nullptr;
+    uint16_t *x16 = nullptr;
     double *part = nullptr;
     uint32_t *tiles64 = nullptr, *tiles128 = nullptr;
     double *lanczos = nullptr;
@@ -75,6 +77,7 @@ struct Ctx {
     int64_t n = 0;
     double n_occ = 0.0, tol = 0.0, kT = 0.0;
     int status = 0;
+    int split_prec = -1;  // split precision whose operand companions are kept
     int last_ntiles = 0;
     int used_tile = 0;
     std::vector<int> phase_launches;

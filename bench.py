@@ -109,6 +109,94 @@ def cpu_baseline(wl, iters_per_solve, budget_s=20.0):
                        f"{iters_per_solve} products ({dt:.1f} s incl. bounds), scaled to one solve")
 
 
+def serving(args):
+    """Continuous-batching server under Poisson arrivals: p50/p99 latency and
+    solves/s, against one-at-a-time FP64 solves of the same requests."""
+    import numpy as np
+    import torch
+
+    import paper_2301_04642_amd as fdm
+    import workloads
+
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(4_999_999)
+    ntemp = 6
+    ns = sorted(set(int(x) for x in np.exp(rng.uniform(np.log(args.n_min), np.log(args.n_max),
+                                                        ntemp))))
+    templates = {}
+    log("building", len(ns) * 2, "templates")
+    for i, n in enumerate(ns):
+        for kind in ("gapped", "metallic"):
+            req = dict(id=100 * i + (kind == "metallic"), n=n, n_occ=n // 4,
+                       kT=0.0 if kind == "gapped" else workloads.gen.KT_500K, seed=5_000_000 + 7 * i)
+            wl = workloads.serving_workload(req)
+            from oracle import density as den
+            f, _ = den.occupations(wl.lam, wl.n_occ, wl.kT)
+            templates[(n, kind)] = (wl, float(np.dot(f, wl.lam)))
+    reqs = []
+    for r in range(args.requests):
+        n = ns[rng.integers(len(ns))]
+        kind = "gapped" if r % 2 == 0 else "metallic"
+        wl, e_ref = templates[(n, kind)]
+        perm = rng.permutation(n)
+        sign = rng.choice([-1.0, 1.0], n)
+        hp = (wl.hp[np.ix_(perm, perm)] * sign[:, None]) * sign[None, :]
+        reqs.append(dict(n=n, n_occ=wl.n_occ, kT=wl.kT, hp=np.ascontiguousarray(hp), e_ref=e_ref))
+    budget = int(args.budget_gb * (1 << 30))
+
+    def run(arrivals):
+        srv = fdm.Server(budget_bytes=budget, max_active=args.max_active, precision=args.precision)
+        t0 = time.perf_counter()
+        tickets = []
+        for q, at in zip(reqs, arrivals):
+            while time.perf_counter() - t0 < at:
+                time.sleep(0.0005)
+            tickets.append((srv.submit(q["hp"], q["n_occ"], q["kT"], 1e-8), time.perf_counter() - t0))
+        lat, worst = [], 0.0
+        t_end = 0.0
+        for (t, t_sub), q in zip(tickets, reqs):
+            rc, d, e, st, times = srv.result(t, q["n"])
+            assert rc == 0, rc
+            worst = max(worst, abs(e - q["e_ref"]))
+            lat.append(times[2] - times[0])
+            t_end = max(t_end, times[2])
+        srv.close()
+        return np.array(lat), worst, time.perf_counter() - t0
+
+    log("closed loop (all requests at t = 0)")
+    lat0, worst0, span0 = run([0.0] * len(reqs))
+    capacity = len(reqs) / span0
+    rate = args.load * capacity
+    gaps = rng.exponential(1.0 / rate, len(reqs))
+    arrivals = list(np.cumsum(gaps) - gaps[0])
+    log(f"open loop at {args.load} x capacity = {rate:.2f} requests/s")
+    lat, worst, span = run(arrivals)
+    log("one at a time, fp64")
+    H = None
+    t0 = time.perf_counter()
+    for q in reqs:
+        H = torch.from_numpy(q["hp"]).cuda()
+        fdm.solve(H, q["n_occ"], q["kT"], 1e-8, "fp64")
+    torch.cuda.synchronize()
+    seq = len(reqs) / (time.perf_counter() - t0)
+    out = {
+        "metric": "serving: solves/s and latency under Poisson arrivals", "unit": "solves/s",
+        "requests": len(reqs), "n_range": [args.n_min, args.n_max], "distinct_n": ns,
+        "precision": args.precision, "max_active": args.max_active, "budget_gb": args.budget_gb,
+        "closed_loop_solves_per_s": round(capacity, 3),
+        "open_loop": {"offered_rate": round(rate, 3), "solves_per_s": round(len(reqs) / span, 3),
+                      "p50_s": round(float(np.percentile(lat, 50)), 4),
+                      "p99_s": round(float(np.percentile(lat, 99)), 4),
+                      "mean_s": round(float(lat.mean()), 4)},
+        "closed_loop_p50_s": round(float(np.percentile(lat0, 50)), 4),
+        "closed_loop_p99_s": round(float(np.percentile(lat0, 99)), 4),
+        "sequential_fp64_solves_per_s": round(seq, 3),
+        "worst_abs_dE_Ha": max(worst, worst0),
+        "data": "synthetic (signed permutations of seeded templates)",
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,7 +211,18 @@ def main():
                                        "fp16x3+lanczos")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (counter calibration)")
+    ap.add_argument("--serving", action="store_true", help="serving measurement instead")
+    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--n-min", type=int, default=500)
+    ap.add_argument("--n-max", type=int, default=4000)
+    ap.add_argument("--max-active", type=int, default=4)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--load", type=float, default=0.8)
     args = ap.parse_args()
+    if args.serving:
+        if args.gpus != 1:
+            sys.exit("serving runs on one GPU")
+        return serving(args)
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the solver has no multi-GPU path "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)

@@ -212,11 +212,13 @@ Resources *thread_resources(int dev) {
 // ---------------------------------------------------------------------------
 int Ctx::tile_for(int prec) const {
     if (opt.tile == 64 || opt.tile == 128) return opt.tile;
-    // FP64 / FP32: 64-wide tiles keep > 4 waves of work on 256 CUs up to
-    // N ~ 8k; larger problems amortise the panel loads with 128-wide tiles.
+    // Measured on MI355X (N = 4000 / 16000): FP64 is fastest with 64-wide
+    // tiles at every size (4 blocks per CU hide the MFMA latency); FP32 and
+    // the 16-bit forms gain from 128-wide tiles (half the panel traffic per
+    // flop) once there are enough of them to fill the 256 CUs several times.
+    if (prec == P_F64) return 64;
     const int64_t t128 = ntiles_for(n, 128);
-    if (prec == P_F64 || prec == P_F32) return (t128 >= 4 * 256) ? 128 : 64;
-    return (t128 >= 2 * 256) ? 128 : 64;
+    return (t128 >= 4 * 256) ? 128 : 64;
 }
 
 int Ctx::product(int prec, const void *A, const void *B, const void *E, void *C,
@@ -631,8 +633,12 @@ int Ctx::solve_zero_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, dou
         if (n > 4000) k64 += (opt.bounds == 1 ? 1 : 5) * (int)ceil(log2((double)n / 4000.0));
         k64 = std::min(std::max(k64, 0), 24);
     }
+    // Leave low precision once every eigenvalue of X is within tau of 0 or 1
+    // (tau << 1/4 keeps each on its side); with the stagnation guard the
+    // phase also ends on its rounding floor, from where one FP64 McWeeny
+    // step (error -> 3 err^2) usually meets tol.
     double tau = opt.tau;
-    if (!(tau > 0.0)) tau = std::max(1e-3, 4.0 * unit_roundoff(prec) * sqrt(n_occ));
+    if (!(tau > 0.0)) tau = std::max(1e-5, 4.0 * unit_roundoff(prec) * sqrt(n_occ));
     void *cur32 = nullptr;
     if (k64 > 0) {
         rc = affine(0, Hp, ldh, 0, X64[0], 0, 0, 1, &np);

@@ -109,6 +109,8 @@ typedef struct fdm_stats {
     double gersh_min, gersh_max;    /* Gershgorin bounds (e_min / e_max hold the bounds used)  */
     int32_t lanczos_steps;      /* Lanczos steps run for the bounds (0 with bounds = 0)        */
     int32_t reserved;
+    double mcweeny_idem[4];     /* zero-T mixed: ||X^2 - X||_F at each FP64 McWeeny check      */
+    double mcweeny_trace_err[4];/* zero-T mixed: |Tr X - n_occ| at each FP64 McWeeny check     */
 } fdm_stats;
 
 /* Fills *opt with the defaults listed above.  Returns FDM_EINVAL if opt is NULL. */

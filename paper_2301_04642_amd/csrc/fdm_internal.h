@@ -53,6 +53,7 @@ struct DevState {
     int32_t switch_mode;             // 1: low-precision phase (stop on tau / stagnation)
     int32_t gprod;                   // global SP2 product counter (branch bits)
     uint64_t bits[4];
+    double mcw_idem[4], mcw_trerr[4];  // FP64 McWeeny checks: ||X^2 - X||, |Tr X - n_occ|
 };
 
 // What the host polls: written by the decide kernel into mapped pinned memory.

@@ -9,12 +9,11 @@
 // error O(4^-m)).  Each step is three kinds of symmetric products of
 // commuting matrices:
 //     S = Y^2,   Z ~ (I + 4S)^-1 by Newton-Schulz,   Y <- 2 Y Z.
-// The Newton-Schulz start Z_0 = 2/(2 + r) I uses the closed-form bound
-// r >= ||4 Y_k^2|| = tanh^2(2^k atanh(2 ||Y_0||)), so ||I - (I+4S) Z_0|| <=
-// r/(2+r) <= 1/3, and the number of iterations that reaches the working
-// precision is known on the host in advance; the first iteration is
-// elementwise (Z_1 = 2cI - c^2 (I + 4S)).  No scalar is read back inside an
-// evaluation.
+// The Newton-Schulz start uses the closed-form bound r >= ||4 Y_k^2|| =
+// tanh^2(2^k atanh(2 ||Y_0||)): the minimax linear polynomial in S (an
+// elementwise step) leaves ||I - (I+4S) Z_1|| <= 1/17, and the number of
+// iterations that reaches the working precision is known on the host in
+// advance.  No scalar is read back inside an evaluation.
 //
 // mu is unknown to the method: Newton on Tr D(mu) = n_occ (dTr/dmu =
 // beta Tr(D - D^2), and Tr D^2 = ||D||_F^2), kept inside a bracket by an
@@ -71,18 +70,31 @@ __global__ __launch_bounds__(256) void k_symdiff(const double *__restrict__ H, i
     }
 }
 
-// Newton-Schulz iterations after the elementwise first one so that the
-// error bound e0^(2^J) reaches `target` (J counts all iterations).
-int ns_iterations(double r, double target) {
-    const double e0 = r / (2.0 + r);
-    if (e0 <= 0.0) return 0;
-    int J = 1;
-    double e = e0 * e0;
+// Start of the inverse iteration for A = I + 4S with spectrum in [1, 1+r]:
+// the linear polynomial Z_1 = a S + b I whose residual I - A Z_1 is the
+// shifted Chebyshev polynomial T_2 scaled to 1 at A = 0, i.e. the smallest
+// possible max |1 - A p(A)| over [1, 1+r] for linear p:
+//   e_1 = r^2 / (2 (2+r)^2 - r^2)      (1/17 at r = 1).
+// It is elementwise in S, so it costs no product.
+struct NsStart {
+    double a, b, e1;
+};
+NsStart ns_start(double r) {
+    if (!(r > 0.0)) return {0.0, 1.0, 0.0};
+    const double c = 2.0 / r, xi0 = -(2.0 + r) / r;
+    const double t0 = 2.0 * xi0 * xi0 - 1.0;
+    return {-8.0 * c * c / t0, -(2.0 * c * c + 4.0 * c * xi0) / t0, 1.0 / t0};
+}
+
+// Newton-Schulz product iterations after Z_1 so that e_1^(2^J) <= target.
+int ns_iterations(double e1, double target) {
+    int J = 0;
+    double e = e1;
     while (e > target && J < 12) {
         e = e * e;
         ++J;
     }
-    return J - 1;
+    return J;
 }
 
 double ns_target(int prec) {
@@ -148,11 +160,10 @@ int Ctx::fermi_operator(const double *Hp, int64_t ldh, double mu, int depth, int
         const double rk = std::min(t * t, 1.0);
         rc = product(prec, Y, Y, nullptr, S, c_sq, nullptr, false, false);
         if (rc) return rc;
-        const double c = 2.0 / (2.0 + rk);
-        rc = affine(lo ? 1 : 0, S, r->lay.ld, lo ? 1 : 0, Z, -4.0 * c * c, 2.0 * c - c * c, 0,
-                    nullptr);
+        const NsStart z1 = ns_start(rk);
+        rc = affine(lo ? 1 : 0, S, r->lay.ld, lo ? 1 : 0, Z, z1.a, z1.b, 0, nullptr);
         if (rc) return rc;
-        const int J = ns_iterations(rk, target);
+        const int J = ns_iterations(z1.e1, target);
         for (int j = 0; j < J; ++j) {
             rc = product(prec, S, Z, Z, W, c_w, nullptr, false, false);
             if (rc) return rc;

@@ -434,6 +434,10 @@ __global__ __launch_bounds__(256) void k_decide(DevState *st, HostMirror *hm,
             const double idem = sqrt(s2);
             st->idem = idem;
             st->executed += 1;
+            if (st->iter < 4) {
+                st->mcw_idem[st->iter] = idem;
+                st->mcw_trerr[st->iter] = fabs(st->trace - st->n_occ);
+            }
             if (idem <= st->tol && fabs(st->trace - st->n_occ) <= st->tol) {
                 st->done = 1;
                 st->result_iter = st->iter;

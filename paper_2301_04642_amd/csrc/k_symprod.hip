@@ -223,10 +223,14 @@ void k_symprod(ProdArgs a) {
     const S *__restrict__ A = (const S *)a.A;
     const S *__restrict__ B = (const S *)a.B;
 
-    u4_t ga[NL], gb[NL];
+    // Two register sets of staged operand chunks: the loads for stage k+2
+    // are issued while stage k is multiplied, so a CU keeps two stages of
+    // panel traffic in flight (the split forms carry little MFMA work per
+    // stage and would otherwise wait on memory latency).
+    u4_t ga0[NL], gb0[NL], ga1[NL], gb1[NL];
     const uint16_t *__restrict__ Ahl = a.Ahl;
     const uint16_t *__restrict__ Bhl = a.Bhl;
-    auto gload = [&](int kt) {
+    auto gload = [&](int kt, u4_t (&ga)[NL], u4_t (&gb)[NL]) {
         const int64_t k0 = (int64_t)kt * KST;
 #pragma unroll
         for (int u = 0; u < NL; ++u) {
@@ -243,7 +247,7 @@ void k_symprod(ProdArgs a) {
             }
         }
     };
-    auto lstore = [&](int st) {
+    auto lstore = [&](int st, const u4_t (&ga)[NL], const u4_t (&gb)[NL]) {
         unsigned char *pa = lds + (st * 2 + 0) * NARR * PANEL;
         unsigned char *pb = lds + (st * 2 + 1) * NARR * PANEL;
 #pragma unroll
@@ -302,16 +306,42 @@ void k_symprod(ProdArgs a) {
         }
     };
 
+    // Stage kt lives in LDS buffer kt & 1; the loop is unrolled by two so
+    // buffer and register-set indices are static.  The split forms prefetch
+    // two stages ahead (register set kt & 1 carries stage kt); FP64 / FP32
+    // carry 4x more MFMA cycles per stage and prefetch one stage ahead.
     const int nk = a.kext / KST;
-    gload(0);
-    lstore(0);
-    __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < nk) gload(kt + 1);
-        compute(cur);
-        if (kt + 1 < nk) lstore(cur ^ 1);
+    if constexpr (SPLIT) {
+        gload(0, ga0, gb0);
+        if (nk > 1) gload(1, ga1, gb1);
+        lstore(0, ga0, gb0);
         __syncthreads();
+        for (int kt = 0; kt < nk; kt += 2) {
+            if (kt + 2 < nk) gload(kt + 2, ga0, gb0);
+            compute(0);
+            if (kt + 1 < nk) lstore(1, ga1, gb1);
+            __syncthreads();
+            if (kt + 1 >= nk) break;
+            if (kt + 3 < nk) gload(kt + 3, ga1, gb1);
+            compute(1);
+            if (kt + 2 < nk) lstore(0, ga0, gb0);
+            __syncthreads();
+        }
+    } else {
+        gload(0, ga0, gb0);
+        lstore(0, ga0, gb0);
+        __syncthreads();
+        for (int kt = 0; kt < nk; kt += 2) {
+            if (kt + 1 < nk) gload(kt + 1, ga0, gb0);
+            compute(0);
+            if (kt + 1 < nk) lstore(1, ga0, gb0);
+            __syncthreads();
+            if (kt + 1 >= nk) break;
+            if (kt + 2 < nk) gload(kt + 2, ga0, gb0);
+            compute(1);
+            if (kt + 2 < nk) lstore(0, ga0, gb0);
+            __syncthreads();
+        }
     }
 
     // ---- fused epilogue -------------------------------------------------

@@ -435,7 +435,14 @@ int Ctx::finish(const double *Hp, int64_t ldh, const void *dm, int dm_f32, doubl
     if (rc) return rc;
     stats.band_energy = h.sums[0];
     stats.trace = h.sums[1];
-    for (int k = 0; k < 4; ++k) stats.branch_bits[k] = h.bits[k];
+    for (int k = 0; k < 4; ++k) {
+        stats.branch_bits[k] = h.bits[k];
+        stats.mcweeny_idem[k] = (k <= stats.mcweeny_steps && stats.mcweeny_steps > 0) ||
+                                        (k == 0 && stats.iters_low > 0)
+                                    ? h.mcw_idem[k]
+                                    : 0.0;
+        stats.mcweeny_trace_err[k] = stats.mcweeny_idem[k] != 0.0 ? h.mcw_trerr[k] : 0.0;
+    }
     if (E_band) *E_band = h.sums[0];
     return FDM_OK;
 }

@@ -205,10 +205,24 @@ def check_fd_recursion_dense(doubling=fd.doubling, n=64):
     assert np.linalg.norm(d - d_ref) < 1e-11, np.linalg.norm(d - d_ref)
 
 
+def check_banded_eigenvalues(banded=den.banded_eigenvalues):
+    """The banded solver on the paper's matrix agrees with Jacobi (and so
+    with the dense definition) once the band holds every non-negligible
+    diagonal; the reference energy is the sum of the lowest eigenvalues."""
+    h = workloads.paper_e1_matrix(96)
+    w = banded(h, 80)
+    wj, _ = jacobi_eigh(h)
+    assert np.abs(w - wj).max() < 1e-13
+    e, mu, f = den.reference_energy(w, 86, 0.0)
+    assert abs(e - np.sort(wj)[:86].sum()) < 1e-12
+    # truncating the band visibly changes the spectrum (the pin is sensitive)
+    assert np.abs(banded(h, 3) - wj).max() > 1e-3
+
+
 ALL_PINS = [
     check_jacobi_2x2, check_jacobi_toeplitz, check_jacobi_known_spectrum, check_jacobi_vs_lapack,
     check_density_invariants, check_density_vs_construction, check_shift_scale_and_permutation,
     check_fd_two_level, check_fd_symmetric_mu, check_fd_low_t_limit, check_gershgorin,
     check_sp2_diagonal, check_sp2_matches_definition, check_mcweeny,
-    check_fd_recursion_closed_form, check_fd_recursion_dense,
+    check_fd_recursion_closed_form, check_fd_recursion_dense, check_banded_eigenvalues,
 ]

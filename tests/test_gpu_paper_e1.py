@@ -1,0 +1,70 @@
+"""The paper's own synthetic projected Hamiltonian (Sec. IV): H_ij =
+exp(-0.5|i-j|) sin(min(i,j)+1) at the paper's smallest size N = 8192, with
+90% occupation at zero temperature and 85% at 500 K.  The reference band
+energy comes from the oracle's banded eigensolver (the matrix is banded to
+rounding beyond 80 diagonals); D is checked through properties that hold at
+any size (trace, idempotency of sampled rows, energy)."""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_util import dev, host, say
+
+pytestmark = pytest.mark.gpu
+
+N = 8192
+
+
+@pytest.fixture(scope="module")
+def e1():
+    from oracle import density as den
+    say("E1 matrix and banded reference spectrum", N)
+    h = workloads.paper_e1_matrix(N)
+    lam = den.banded_eigenvalues(h, 80)
+    return h, lam
+
+
+@pytest.fixture(scope="module")
+def fdm():
+    import paper_2301_04642_amd as m
+    return m
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x3"])
+def test_e1_zero_t(fdm, e1, prec):
+    from oracle import density as den
+    h, lam = e1
+    n_occ = int(round(0.9 * N))
+    e_ref, _, _ = den.reference_energy(lam, n_occ, 0.0)
+    say("E1 zero-T", prec)
+    D, e, st = fdm.solve(dev(h), n_occ, 0.0, 1e-8, prec)
+    d = host(D)
+    rows = np.random.default_rng(8).choice(N, 4, replace=False)
+    idem_rows = np.linalg.norm(d[rows] @ d - d[rows])
+    print(f"[report] E1 N={N} {prec}: iters {st.iters_fp64}/{st.iters_fp64_first}/{st.iters_low}/"
+          f"mcw{st.mcweeny_steps} |dE|={abs(e - e_ref):.2e} eps2={(e - e_ref) / e_ref:.1e} "
+          f"|dTr|={abs(np.trace(d) - n_occ):.2e} idem={st.idempotency:.1e} "
+          f"rows idem={idem_rows:.1e} bounds=({st.e_min:.3f},{st.e_max:.3f}) {st.ms_total:.0f} ms",
+          flush=True)
+    assert st.status == 0
+    assert abs(np.trace(d) - n_occ) <= 1e-8
+    assert st.idempotency <= 1e-8 and idem_rows <= 1e-8
+    assert abs(e - e_ref) <= (1e-8 if prec == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16x3"])
+def test_e1_finite_t(fdm, e1, prec):
+    from oracle import density as den
+    h, lam = e1
+    n_occ = 0.85 * N
+    kT = workloads.gen.KT_500K
+    e_ref, mu, f = den.reference_energy(lam, n_occ, kT)
+    say("E1 finite-T", prec)
+    D, e, st = fdm.solve(dev(h), n_occ, kT, 1e-9 if prec == "fp64" else 1e-6, prec)
+    d = host(D)
+    print(f"[report] E1 N={N} finite-T {prec}: evals {st.mu_evals} depth {st.depth} "
+          f"mu={st.mu:.9f} (exact {mu:.9f}) |dE|={abs(e - e_ref):.2e} "
+          f"|dTr|={abs(np.trace(d) - n_occ):.2e} {st.ms_total:.0f} ms", flush=True)
+    assert st.status == 0
+    assert abs(np.trace(d) - n_occ) <= 1e-8
+    assert abs(e - e_ref) <= (1e-9 if prec == "fp64" else 1e-6)

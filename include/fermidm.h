@@ -79,7 +79,7 @@ typedef struct fdm_options {
                                tightened by a Lanczos estimate of the extreme eigenvalues
                                (Ritz values widened by their residual bounds and 1% of the
                                width, never outside the Gershgorin interval)                  */
-    int32_t lanczos_steps;  /* Lanczos steps for bounds = 1 (default 32, at most 64)           */
+    int32_t lanczos_steps;  /* Lanczos steps for bounds = 1 (default 16, at most 64)           */
     int32_t reserved;
     void *workspace;        /* optional caller-owned device memory of workspace_bytes          */
     size_t workspace_bytes; /* at least fdm_workspace_bytes(N, kT, precision)                  */

@@ -523,7 +523,7 @@ static void small_eigh(int k, std::vector<double> &a, std::vector<double> &w,
 // last component of T_k's eigenvector).  The bounds are theta -+ (residual +
 // 1% of the Ritz width), clipped to the Gershgorin interval in *h.
 int Ctx::refine_bounds(const double *Hp, int64_t ldh, DevState *h) {
-    int k = opt.lanczos_steps > 0 ? std::min(opt.lanczos_steps, kMaxLanczos) : 32;
+    int k = opt.lanczos_steps > 0 ? std::min(opt.lanczos_steps, kMaxLanczos) : 16;
     k = (int)std::min<int64_t>(k, n);
     if (k < 2) return FDM_OK;
     double *ab = r->lanczos + 3 * r->lay.np;
@@ -725,7 +725,7 @@ int fdm_options_default(fdm_options *opt) {
     opt->timing = 0;
     opt->tile = 0;
     opt->bounds = 1;
-    opt->lanczos_steps = 32;
+    opt->lanczos_steps = 16;
     return FDM_OK;
 }
 

@@ -274,15 +274,29 @@ void k_symprod(ProdArgs a) {
 
     const int w = tid >> 6, lane = tid & 63;
     const int wr = w >> 1, wc = w & 1, lr = lane & 15, lg = lane >> 4;
-    Acc acc[FM][FM];
+    // FP32-accumulating forms sum each K stage in a fresh accumulator and
+    // fold it into the running sum with a compensated (two-sum) add: the
+    // accumulation error then grows with the stage length (32) instead of
+    // with N, which lowers the rounding floor of the low-precision SP2
+    // iterates ~30x (the operand rounding is what remains).
+    constexpr bool COMP = (P != P_F64);
+    Acc acc[FM][FM], cmp[FM][FM];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FM; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+        for (int j = 0; j < FM; ++j) {
+            acc[i][j] = Acc{0, 0, 0, 0};
+            cmp[i][j] = Acc{0, 0, 0, 0};
+        }
 
     auto compute = [&](int st) {
         const unsigned char *pa = lds + (st * 2 + 0) * NARR * PANEL;
         const unsigned char *pb = lds + (st * 2 + 1) * NARR * PANEL;
+        Acc part[FM][FM];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FM; ++j) part[i][j] = Acc{0, 0, 0, 0};
 #pragma unroll
         for (int g = 0; g < GROUPS; ++g) {
             u4_t fa[FM], fb[FM], fal[FM], fbl[FM];
@@ -301,8 +315,26 @@ void k_symprod(ProdArgs a) {
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
+                for (int j = 0; j < FM; ++j) {
+                    if constexpr (COMP)
+                        part[i][j] = mfma_frag<P>(fa[i], fb[j], fal[i], fbl[j], part[i][j]);
+                    else
+                        acc[i][j] = mfma_frag<P>(fa[i], fb[j], fal[i], fbl[j], acc[i][j]);
+                }
+        }
+        if constexpr (COMP) {
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
                 for (int j = 0; j < FM; ++j)
-                    acc[i][j] = mfma_frag<P>(fa[i], fb[j], fal[i], fbl[j], acc[i][j]);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        // Kahan: cmp holds the low-order part lost so far
+                        const float y = part[i][j][q] - cmp[i][j][q];
+                        const float t = acc[i][j][q] + y;
+                        cmp[i][j][q] = (t - acc[i][j][q]) - y;
+                        acc[i][j][q] = t;
+                    }
         }
     };
 
@@ -366,7 +398,7 @@ void k_symprod(ProdArgs a) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t row = rb + (ROWS_CONSECUTIVE ? 4 * lg + q : lg + 4 * q);
-                const double v = (double)acc[i][j][q] * scale;
+                const double v = ((double)acc[i][j][q] - (double)cmp[i][j][q]) * scale;
                 const double e = (E != nullptr) ? (double)E[row * ld + col] : 0.0;
                 double o = alpha * v + beta * e;
                 if (row == col && row < a.n) o += gamma;

@@ -16,8 +16,9 @@
 // advance.  No scalar is read back inside an evaluation.
 //
 // mu is unknown to the method: Newton on Tr D(mu) = n_occ (dTr/dmu =
-// beta Tr(D - D^2), and Tr D^2 = ||D||_F^2), kept inside a bracket by an
-// Illinois regula falsi, optionally in low precision, then one FP64
+// beta Tr(D - D^2), and Tr D^2 = ||D||_F^2), safeguarded by bisection on a
+// bracket and started from the Lanczos quadrature of the spectral density,
+// optionally in low precision, then one FP64
 // evaluation at the final mu and the second-order canonical correction
 // D <- D + u (D - D^2) + u^2/2 (D - 3D^2 + 2D^3), u = beta dmu.
 #include <math.h>
@@ -234,7 +235,7 @@ int Ctx::canonical_correction(void *dm, double tr, double trdd, double *mu, void
     rc = product(P_F64, P, D, Q, out_buf, coef, nullptr, false, false);
     if (rc) return rc;
     close_phase(2);
-    *mu += u / kT;
+    *mu += u * kT;  // u = beta dmu
     *out = out_buf;
     return FDM_OK;
 }
@@ -251,18 +252,36 @@ int Ctx::solve_finite_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, d
     const int extra = opt.fd_extra_depth;
     const int pe = opt.precision;  // precision of the mu search
     split_prec = pe;
-    // start: uniform-density-of-states guess from the exact moments
-    const double m1 = h.trH / (double)n;
-    const double m2 = std::max(h.fro2H / (double)n - m1 * m1, 0.0);
-    double mu = m1 + sqrt(3.0 * m2) * (2.0 * n_occ / (double)n - 1.0);
+    // start: with the Lanczos quadrature of the spectral density (bounds = 1),
+    // the mu at which N sum_i w_i f(theta_i - mu) = n_occ, f smoothed over
+    // the Ritz-value spacing; otherwise the uniform-density guess from the
+    // exact moments.
+    double mu;
+    if (ritz.size() >= 2) {
+        const double tq = std::max(kT, 0.5 * (ritz.back() - ritz.front()) / (double)ritz.size());
+        double a = ritz.front() - 40.0 * tq, b = ritz.back() + 40.0 * tq;
+        for (int it = 0; it < 200; ++it) {
+            const double mid = 0.5 * (a + b);
+            double cnt = 0.0;
+            for (size_t i = 0; i < ritz.size(); ++i)
+                cnt += ritz_w[i] * 0.5 * (1.0 - tanh((ritz[i] - mid) / (2.0 * tq)));
+            if ((double)n * cnt < n_occ)
+                a = mid;
+            else
+                b = mid;
+        }
+        mu = 0.5 * (a + b);
+    } else {
+        const double m1 = h.trH / (double)n;
+        const double m2 = std::max(h.fro2H / (double)n - m1 * m1, 0.0);
+        mu = m1 + sqrt(3.0 * m2) * (2.0 * n_occ / (double)n - 1.0);
+    }
     // bracket: Tr D(e_min) ~ 0 < n_occ < N ~ Tr D(e_max)
     double lo = h.emin, hi = h.emax;
     if (!(hi > lo)) {
         lo -= 1.0;
         hi += 1.0;
     }
-    double f_lo = -n_occ, f_hi = (double)n - n_occ;
-    int side = 0;  // Illinois: which end was kept last (-1 lo, +1 hi)
     mu = std::min(std::max(mu, lo + 1e-3 * (hi - lo)), hi - 1e-3 * (hi - lo));
     void *dm = nullptr;
     int dm_f32 = 0;
@@ -285,28 +304,19 @@ int Ctx::solve_finite_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, d
             converged = true;
             break;
         }
-        if (err < 0.0) {
+        if (err < 0.0)
             lo = mu;
-            f_lo = err;
-            if (side == -1) f_hi *= 0.5;
-            side = -1;
-        } else {
+        else
             hi = mu;
-            f_hi = err;
-            if (side == 1) f_lo *= 0.5;
-            side = 1;
-        }
         const double step = (trdd > 1e-300) ? -err / (beta * trdd) : 0.0;
         if (trdd > 1e-300 && fabs(step) * beta <= u_stop) {
             converged = true;
             break;
         }
+        // Newton inside the bracket, else bisection (Tr D(mu) is flat across
+        // gaps of the spectrum, where the Newton step runs away)
         double next = mu + step;
-        if (!(trdd > 1e-300) || !(next > lo && next < hi)) {
-            // regula falsi on the bracket (Illinois-weighted)
-            next = (lo * f_hi - hi * f_lo) / (f_hi - f_lo);
-            if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
-        }
+        if (!(trdd > 1e-300) || !(next > lo && next < hi)) next = 0.5 * (lo + hi);
         mu = next;
     }
     if (pe != P_F64) {

@@ -279,7 +279,10 @@ void k_symprod(ProdArgs a) {
     // accumulation error then grows with the stage length (32) instead of
     // with N, which lowers the rounding floor of the low-precision SP2
     // iterates ~30x (the operand rounding is what remains).
-    constexpr bool COMP = (P != P_F64);
+    // (64-wide tiles only: a 128-wide tile runs one wave per SIMD, where the
+    // extra VALU work serialises with the MFMAs and costs more than the
+    // FP64 refinement step it saves.)
+    constexpr bool COMP = (P != P_F64) && BT == 64;
     Acc acc[FM][FM], cmp[FM][FM];
 #pragma unroll
     for (int i = 0; i < FM; ++i)

@@ -212,11 +212,12 @@ Resources *thread_resources(int dev) {
 // ---------------------------------------------------------------------------
 int Ctx::tile_for(int prec) const {
     if (opt.tile == 64 || opt.tile == 128) return opt.tile;
-    // Measured on MI355X (N = 4000 / 16000): FP64 is fastest with 64-wide
-    // tiles at every size (4 blocks per CU hide the MFMA latency); FP32 and
-    // the 16-bit forms gain from 128-wide tiles (half the panel traffic per
-    // flop) once there are enough of them to fill the 256 CUs several times.
-    if (prec == P_F64) return 64;
+    // Measured on MI355X (N = 4000 / 16000): FP64 and FP32 are fastest with
+    // 64-wide tiles at every size (4 blocks per CU hide the MFMA latency; the
+    // FP32 tiles also carry the compensated accumulation); the 16-bit forms
+    // gain from 128-wide tiles (half the panel traffic per flop) once there
+    // are enough of them to fill the 256 CUs several times.
+    if (prec == P_F64 || prec == P_F32) return 64;
     const int64_t t128 = ntiles_for(n, 128);
     return (t128 >= 4 * 256) ? 128 : 64;
 }
@@ -554,6 +555,12 @@ int Ctx::refine_bounds(const double *Hp, int64_t ldh, DevState *h) {
         if (w[i] < w[imin]) imin = i;
         if (w[i] > w[imax]) imax = i;
     }
+    // Gauss quadrature of the spectral density: Ritz values with the squared
+    // first components of T's eigenvectors as weights (used to start the
+    // chemical-potential search at finite temperature).
+    ritz.assign(w.begin(), w.end());
+    ritz_w.resize(m);
+    for (int i = 0; i < m; ++i) ritz_w[i] = V[i] * V[i];
     const double bk = (m == k) ? beta[k - 1] : 0.0;
     const double rmin = fabs(bk * V[(size_t)(m - 1) * m + imin]);
     const double rmax = fabs(bk * V[(size_t)(m - 1) * m + imax]);

@@ -81,6 +81,7 @@ struct Ctx {
     int last_ntiles = 0;
     int used_tile = 0;
     std::vector<int> phase_launches;
+    std::vector<double> ritz, ritz_w;  // Lanczos Ritz values and Gauss weights of Hp
     std::vector<Timed> timed;
 
     int tile_for(int prec) const;

@@ -111,6 +111,9 @@ typedef struct fdm_stats {
     int32_t reserved;
     double mcweeny_idem[4];     /* zero-T mixed: ||X^2 - X||_F at each FP64 McWeeny check      */
     double mcweeny_trace_err[4];/* zero-T mixed: |Tr X - n_occ| at each FP64 McWeeny check     */
+    double mu_hist[16];         /* finite T: mu of the first 16 Fermi-operator evaluations      */
+    double mu_trace_err[16];    /* finite T: Tr D(mu) - n_occ at those evaluations (their own   */
+                                /*   precision); mu_evals says how many entries are valid       */
 } fdm_stats;
 
 /* Fills *opt with the defaults listed above.  Returns FDM_EINVAL if opt is NULL. */

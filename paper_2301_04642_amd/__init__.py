@@ -53,7 +53,8 @@ class fdm_stats(ctypes.Structure):
                 ("prod_ms", ctypes.c_double * FDM_NPREC), ("flops", ctypes.c_double * FDM_NPREC),
                 ("gersh_min", ctypes.c_double), ("gersh_max", ctypes.c_double),
                 ("lanczos_steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("mcweeny_idem", ctypes.c_double * 4), ("mcweeny_trace_err", ctypes.c_double * 4)]
+                ("mcweeny_idem", ctypes.c_double * 4), ("mcweeny_trace_err", ctypes.c_double * 4),
+                ("mu_hist", ctypes.c_double * 16), ("mu_trace_err", ctypes.c_double * 16)]
 
     def as_dict(self):
         d = {}

@@ -16,11 +16,10 @@
 // advance.  No scalar is read back inside an evaluation.
 //
 // mu is unknown to the method: Newton on Tr D(mu) = n_occ (dTr/dmu =
-// beta Tr(D - D^2), and Tr D^2 = ||D||_F^2), safeguarded by bisection on a
-// bracket and started from the Lanczos quadrature of the spectral density,
-// optionally in low precision, then one FP64
-// evaluation at the final mu and the second-order canonical correction
-// D <- D + u (D - D^2) + u^2/2 (D - 3D^2 + 2D^3), u = beta dmu.
+// beta Tr(D - D^2), and Tr D^2 = ||D||_F^2), kept in a bracket by regula
+// falsi (bisection on flat stretches), optionally in low precision first,
+// then FP64 evaluations (normally one) and the second-order canonical
+// correction D <- D + u (D - D^2) + u^2/2 (D - 3D^2 + 2D^3), u = beta dmu.
 #include <math.h>
 #include <string.h>
 
@@ -252,11 +251,15 @@ int Ctx::solve_finite_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, d
     const int extra = opt.fd_extra_depth;
     const int pe = opt.precision;  // precision of the mu search
     split_prec = pe;
-    // start: with the Lanczos quadrature of the spectral density (bounds = 1),
-    // the mu at which N sum_i w_i f(theta_i - mu) = n_occ, f smoothed over
-    // the Ritz-value spacing; otherwise the uniform-density guess from the
-    // exact moments.
-    double mu;
+    // Start: the uniform-density guess from the exact moments.  The Lanczos
+    // Gauss quadrature of the spectral density (bounds = 1; one random start
+    // vector, so its count carries a statistical error of ~sqrt(2 n_occ)
+    // states) gives a second guess, tried once when the first Newton step
+    // fails: it sees gaps in the spectrum that the uniform guess cannot.
+    const double m1 = h.trH / (double)n;
+    const double m2 = std::max(h.fro2H / (double)n - m1 * m1, 0.0);
+    double mu = m1 + sqrt(3.0 * m2) * (2.0 * n_occ / (double)n - 1.0);
+    double mu_quad = NAN;
     if (ritz.size() >= 2) {
         const double tq = std::max(kT, 0.5 * (ritz.back() - ritz.front()) / (double)ritz.size());
         double a = ritz.front() - 40.0 * tq, b = ritz.back() + 40.0 * tq;
@@ -270,11 +273,7 @@ int Ctx::solve_finite_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, d
             else
                 b = mid;
         }
-        mu = 0.5 * (a + b);
-    } else {
-        const double m1 = h.trH / (double)n;
-        const double m2 = std::max(h.fro2H / (double)n - m1 * m1, 0.0);
-        mu = m1 + sqrt(3.0 * m2) * (2.0 * n_occ / (double)n - 1.0);
+        mu_quad = 0.5 * (a + b);
     }
     // bracket: Tr D(e_min) ~ 0 < n_occ < N ~ Tr D(e_max)
     double lo = h.emin, hi = h.emax;
@@ -282,44 +281,79 @@ int Ctx::solve_finite_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, d
         lo -= 1.0;
         hi += 1.0;
     }
+    double f_lo = -n_occ, f_hi = (double)n - n_occ;
+    int side = 0;  // Illinois: which end was kept last (-1 lo, +1 hi)
     mu = std::min(std::max(mu, lo + 1e-3 * (hi - lo)), hi - 1e-3 * (hi - lo));
     void *dm = nullptr;
     int dm_f32 = 0;
     double tr = 0.0, trdd = 0.0;
     int evals = 0, depth = 0;
     const int max_evals = std::max(1, opt.max_mu_evals);
+    // One search in precision p: safeguarded Newton on Tr D(mu) = n_occ.
+    // Ends once |Tr D - n_occ| <= tol, or once the Newton step is so small
+    // (|beta dmu| <= u_stop) that the second-order canonical correction
+    // finishes the job; returns whether it ended so within max_evals.
+    auto search = [&](int p, double u_stop, bool *converged) -> int {
+        *converged = false;
+        for (int k = 0; k < max_evals; ++k) {
+            depth = fd_depth(beta, h.emin, h.emax, mu, extra);
+            int rc2 = fermi_operator(Hp, ldh, mu, depth, p, &dm, &dm_f32, &tr, &trdd);
+            if (rc2) return rc2;
+            const double err = tr - n_occ;
+            if (evals < 16) {
+                stats.mu_hist[evals] = mu;
+                stats.mu_trace_err[evals] = err;
+            }
+            ++evals;
+            if (fabs(err) <= tol) {
+                *converged = true;
+                return FDM_OK;
+            }
+            if (err < 0.0) {
+                lo = mu;
+                f_lo = err;
+                if (side == -1) f_hi *= 0.5;
+                side = -1;
+            } else {
+                hi = mu;
+                f_hi = err;
+                if (side == 1) f_lo *= 0.5;
+                side = 1;
+            }
+            const double step = (trdd > 1e-300) ? -err / (beta * trdd) : 0.0;
+            if (trdd > 1e-300 && fabs(step) * beta <= u_stop) {
+                *converged = true;
+                return FDM_OK;
+            }
+            if (hi - lo <= u_stop * kT) {
+                // the bracket is below the resolution asked for
+                *converged = true;
+                return FDM_OK;
+            }
+            double next = mu + step;
+            if (!(trdd > 1e-300) || !(next > lo && next < hi)) {
+                if (mu_quad > lo && mu_quad < hi) {
+                    next = mu_quad;  // once
+                } else if (beta * trdd < 0.05 * (f_hi - f_lo) / (hi - lo)) {
+                    // flat stretch (a gap in the spectrum): bisection
+                    next = 0.5 * (lo + hi);
+                } else {
+                    // regula falsi on the bracket (Illinois-weighted)
+                    next = (lo * f_hi - hi * f_lo) / (f_hi - f_lo);
+                    if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
+                }
+                mu_quad = NAN;
+            }
+            mu = next;
+        }
+        return FDM_OK;
+    };
     bool converged = false;
-    // FP64 search: stop once |Tr D - n_occ| <= tol or the Newton step is so
-    // small (|beta dmu| <= 1e-3) that the second-order correction is exact to
-    // O(1e-10); low-precision search: stop at |beta dmu| <= 1e-4 (below the
-    // trace noise of FP32-class products).
-    const double u_stop = (pe == P_F64) ? 1e-3 : 1e-4;
-    while (evals < max_evals) {
-        depth = fd_depth(beta, h.emin, h.emax, mu, extra);
-        rc = fermi_operator(Hp, ldh, mu, depth, pe, &dm, &dm_f32, &tr, &trdd);
-        if (rc) return rc;
-        ++evals;
-        const double err = tr - n_occ;
-        if (fabs(err) <= tol) {
-            converged = true;
-            break;
-        }
-        if (err < 0.0)
-            lo = mu;
-        else
-            hi = mu;
-        const double step = (trdd > 1e-300) ? -err / (beta * trdd) : 0.0;
-        if (trdd > 1e-300 && fabs(step) * beta <= u_stop) {
-            converged = true;
-            break;
-        }
-        // Newton inside the bracket, else bisection (Tr D(mu) is flat across
-        // gaps of the spectrum, where the Newton step runs away)
-        double next = mu + step;
-        if (!(trdd > 1e-300) || !(next > lo && next < hi)) next = 0.5 * (lo + hi);
-        mu = next;
-    }
     if (pe != P_F64) {
+        // low-precision search: stop at |beta dmu| <= 1e-4 (below the trace
+        // noise of FP32-class products); its result is not checked
+        rc = search(pe, 1e-4, &converged);
+        if (rc) return rc;
         if (!opt.fd_final_fp64) {
             // low precision end to end (reported, not gated): promote D
             int np = 0;
@@ -327,12 +361,23 @@ int Ctx::solve_finite_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, d
             if (rc) return rc;
             dm = r->x64;
             dm_f32 = 0;
-        } else {
-            depth = fd_depth(beta, h.emin, h.emax, mu, extra);
-            rc = fermi_operator(Hp, ldh, mu, depth, P_F64, &dm, &dm_f32, &tr, &trdd);
-            if (rc) return rc;
-            ++evals;
         }
+    }
+    if (pe == P_F64 || opt.fd_final_fp64) {
+        // FP64: after a low-precision search this normally ends after its
+        // first evaluation; |beta dmu| <= 1e-3 leaves the second-order
+        // correction exact to O(1e-10).  The bracket starts afresh: the
+        // low-precision traces carry rounding errors, so their bracket may
+        // just miss the FP64 root.
+        if (pe != P_F64) {
+            lo = h.emax > h.emin ? h.emin : h.emin - 1.0;
+            hi = h.emax > h.emin ? h.emax : h.emax + 1.0;
+            f_lo = -n_occ;
+            f_hi = (double)n - n_occ;
+            side = 0;
+        }
+        rc = search(P_F64, 1e-3, &converged);
+        if (rc) return rc;
     }
     stats.mu_evals = evals;
     stats.depth = depth;
@@ -343,7 +388,7 @@ int Ctx::solve_finite_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, d
         dm = out;
     }
     stats.mu = mu;
-    if (!converged && pe == P_F64) status = FDM_ENOCONV;
+    if (!converged && (pe == P_F64 || opt.fd_final_fp64)) status = FDM_ENOCONV;
     return finish(Hp, ldh, dm, dm_f32, D, ldd, E_band);
 }
 

@@ -648,10 +648,11 @@ int Ctx::solve_zero_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, dou
         k64 = std::min(std::max(k64, 0), 24);
     }
     // Leave low precision once every eigenvalue of X is within tau of 0 or 1
-    // (tau << 1/4 keeps each on its side).  The FP32-accumulated products
-    // floor near ||X^2 - X||_F ~ 3e-4 at N = 4000 (measured), and the step
-    // that takes the iterate below tau lands there, so a lower tau only adds
-    // low-precision steps; the stagnation guard ends the phase on that floor.
+    // (tau << 1/4 keeps each on its side).  The low-precision iterates floor
+    // near ||X^2 - X||_F ~ 1e-5 (FP32, compensated) to 1e-4 (split 16-bit
+    // forms) at N = 4000 (measured), and the quadratic step that takes the
+    // iterate below tau lands near that floor, so a lower tau only adds
+    // low-precision steps; the stagnation guard ends the phase on the floor.
     double tau = opt.tau;
     if (!(tau > 0.0)) tau = std::max(1e-3, 4.0 * unit_roundoff(prec) * sqrt(n_occ));
     void *cur32 = nullptr;

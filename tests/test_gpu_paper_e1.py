@@ -65,6 +65,9 @@ def test_e1_finite_t(fdm, e1, prec):
     print(f"[report] E1 N={N} finite-T {prec}: evals {st.mu_evals} depth {st.depth} "
           f"mu={st.mu:.9f} (exact {mu:.9f}) |dE|={abs(e - e_ref):.2e} "
           f"|dTr|={abs(np.trace(d) - n_occ):.2e} {st.ms_total:.0f} ms", flush=True)
+    k = min(st.mu_evals, 16)
+    print("[report]   mu search: " + " ".join(
+        f"({st.mu_hist[i]:.6f},{st.mu_trace_err[i]:+.2e})" for i in range(k)), flush=True)
     assert st.status == 0
     assert abs(np.trace(d) - n_occ) <= 1e-8
     assert abs(e - e_ref) <= (1e-9 if prec == "fp64" else 1e-6)

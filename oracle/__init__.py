@@ -11,9 +11,11 @@ computes, written from the paper (arXiv 2301.04642):
   in the paper's order, with Gershgorin spectral bounds (Sec. II.C) and
   McWeeny refinement.
 * ``fd``: the finite-temperature doubling recursion and its closed form.
+* ``azrfoe``: the accelerated zero-temperature expansion of Sec. II.B.2
+  (shifted and scaled SP2 polynomials chosen from HOMO/LUMO bounds).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  It shares no code with the GPU library
 and never calls it.
 """
-from . import density, fd, sp2  # noqa: F401
+from . import azrfoe, density, fd, sp2  # noqa: F401

@@ -8,6 +8,7 @@ import math
 import numpy as np
 
 from oracle import density as den
+from oracle import azrfoe as az
 from oracle import fd, sp2
 from oracle.eig import jacobi_eigh
 import workloads
@@ -219,10 +220,92 @@ def check_banded_eigenvalues(banded=den.banded_eigenvalues):
     assert np.abs(banded(h, 3) - wj).max() > 1e-3
 
 
+def check_azrfoe_fold(step=az.step_polynomial):
+    """Each accelerated polynomial keeps the converged end fixed (1 -> 1 for
+    the squaring form, 0 -> 0 for the other), folds the squared interval so
+    its two ends meet, maps both assumed intervals into [0, 1], and reports
+    the images of the interval ends as the next bounds."""
+    rng = np.random.default_rng(31)
+    for _ in range(200):
+        l, h = np.sort(rng.uniform(0.0, 1.0, 2))
+        (a, b, c), br, s, l2, h2 = step(l, h)
+        p = lambda x: a * x * x + b * x + c  # noqa: E731
+        if br == 1:
+            assert abs(p(1.0) - 1.0) < 1e-12 and abs(p(0.0) - p(l)) < 1e-12
+        else:
+            assert abs(p(0.0)) < 1e-12 and abs(p(1.0) - p(h)) < 1e-12
+        xs_u = np.linspace(0.0, l, 101)
+        xs_o = np.linspace(h, 1.0, 101)
+        assert abs(p(xs_u).max() - l2) < 1e-12 and p(xs_u).min() >= -1e-12
+        assert abs(p(xs_o).min() - h2) < 1e-12 and p(xs_o).max() <= 1.0 + 1e-12
+        # the squared error shrinks at least 4x faster than under X^2 / 2X - X^2
+        if br == 1:
+            assert l2 <= l * l / 4.0 * (1.0 + 1e-12) / (1.0 - l / 2.0) ** 2
+        else:
+            assert 1.0 - h2 <= (1.0 - h) ** 2 / 4.0 * (1.0 + 1e-12) / (1.0 - (1.0 - h) / 2.0) ** 2
+
+
+def check_azrfoe_diagonal(azfn=az.azrfoe):
+    """On a diagonal H with exact bounds, every eigenvalue follows the scalar
+    polynomial sequence, and the recorded bounds are attained: the largest
+    unoccupied image equals l_n and the smallest occupied image equals h_n."""
+    rng = np.random.default_rng(23)
+    n, n_occ = 30, 11
+    lam = np.sort(np.concatenate([rng.uniform(-1, -0.25, n_occ), rng.uniform(0.05, 1, n - n_occ)]))
+    x, info = azfn(np.diag(lam), n_occ, lam[n_occ - 1], lam[n_occ], tol=1e-12)
+    assert info["converged"]
+    lo, hi = lam.min(), lam.max()
+    v = (hi - lam) / (hi - lo)
+    occ = np.arange(n) < n_occ
+    for k, (br, s) in enumerate(zip(info["branches"], info["shifts"])):
+        l_k, h_k = info["intervals"][k]
+        assert abs(v[~occ].max() - l_k) < 1e-12 and abs(v[occ].min() - h_k) < 1e-12, k
+        v = ((v - s) / (1 - s)) ** 2 if br else 1 - ((1 - s - v) / (1 - s)) ** 2
+    assert np.allclose(np.diag(x), v, atol=1e-14, rtol=0)
+    assert np.abs(x - np.diag(np.diag(x))).max() == 0.0
+    assert np.allclose(np.diag(x), occ.astype(float), atol=1e-6)
+
+
+def check_azrfoe_matches_definition(azfn=az.azrfoe, sizes=(16, 64, 256), shrink=(0.0, 0.4)):
+    """Dense H: the accelerated expansion reaches the definition theta(mu - H)
+    with exact HOMO/LUMO bounds and with bounds that understate the gap."""
+    for n in sizes:
+        wl = workloads.config_workload(0, n=n)
+        k = int(wl.n_occ)
+        lam = np.sort(wl.lam)
+        gap = lam[k] - lam[k - 1]
+        f, _ = den.occupations(wl.lam, wl.n_occ, 0.0)
+        d_ref, e_ref = den.density_from_eig(wl.q, wl.lam, f)
+        for c in shrink:
+            x, info = azfn(wl.hp, wl.n_occ, lam[k - 1] + c * gap / 2, lam[k] - c * gap / 2,
+                           tol=1e-11)
+            assert info["converged"], (n, c)
+            assert np.linalg.norm(x - d_ref) < 1e-10, (n, c, np.linalg.norm(x - d_ref))
+            assert abs(den.band_energy(wl.hp, x) - e_ref) < 1e-10
+
+
+def check_azrfoe_paper_counts(count=az.scalar_iterations):
+    """Sec. IV: on the paper's matrix the plain expansion takes about 50
+    products and the accelerated one about 30.  On the exact spectrum of the
+    N = 8192 matrix (banded solver), with the extreme eigenvalues as spectral
+    bounds, 90% occupation and the HOMO/LUMO eigenvalues as the accelerated
+    form's bounds, the two counts land there."""
+    n = 8192
+    lam = den.banded_eigenvalues(workloads.paper_e1_matrix(n), 80)
+    lo, hi = lam[0], lam[-1]
+    k = int(0.9 * n)
+    plain = count(lam, k, 1e-8, lo, hi)
+    acc = count(lam, k, 1e-8, lo, hi, lam[k - 1], lam[k])
+    assert 45 <= plain <= 55, plain
+    assert 24 <= acc <= 34, acc
+
+
 ALL_PINS = [
     check_jacobi_2x2, check_jacobi_toeplitz, check_jacobi_known_spectrum, check_jacobi_vs_lapack,
     check_density_invariants, check_density_vs_construction, check_shift_scale_and_permutation,
     check_fd_two_level, check_fd_symmetric_mu, check_fd_low_t_limit, check_gershgorin,
     check_sp2_diagonal, check_sp2_matches_definition, check_mcweeny,
     check_fd_recursion_closed_form, check_fd_recursion_dense, check_banded_eigenvalues,
+    check_azrfoe_fold, check_azrfoe_diagonal, check_azrfoe_matches_definition,
+    check_azrfoe_paper_counts,
 ]

@@ -156,3 +156,41 @@ def test_golden_e1_finite_t():
     m = fd.depth(1.0 / kT, w.min(), w.max(), mu, extra=8)
     dm = fd.doubling(h, mu, 1.0 / kT, m)
     assert np.abs(dm - d).max() < 1e-11
+
+
+def _az_step_variant(half=0.5, drop_linear=False, unshifted_bound=False, flip=False):
+    """A copy of the accelerated step with one planted mistake."""
+    def step(l, h):
+        e_u, e_o = l, 1.0 - h
+        if (e_u >= e_o) != flip:
+            s = half * e_u
+            k = 1.0 / (1.0 - s) ** 2
+            coef = (k, 0.0 if drop_linear else -2.0 * k * s, k * s * s)
+            h2 = k * h * h if unshifted_bound else k * (h - s) ** 2
+            return coef, 1, s, k * max(s, e_u - s) ** 2, h2
+        s = half * e_o
+        k = 1.0 / (1.0 - s) ** 2
+        u = 1.0 - s
+        coef = (-k, 0.0 if drop_linear else 2.0 * k * u, 1.0 - k * u * u)
+        return coef, 0, s, 1.0 - k * (u - l) ** 2, 1.0 - k * max(s, e_o - s) ** 2
+    return step
+
+
+def test_mutant_azrfoe_fold_point():
+    assert _fails(pins.check_azrfoe_fold, step=_az_step_variant(half=1.0))
+
+
+def test_mutant_azrfoe_dropped_linear_term():
+    assert _fails(pins.check_azrfoe_fold, step=_az_step_variant(drop_linear=True))
+
+
+def test_mutant_azrfoe_unshifted_bound(monkeypatch):
+    from oracle import azrfoe as az
+    monkeypatch.setattr(az, "step_polynomial", _az_step_variant(unshifted_bound=True))
+    assert _fails(pins.check_azrfoe_diagonal, azfn=az.azrfoe)
+
+
+def test_mutant_azrfoe_branch_flipped(monkeypatch):
+    from oracle import azrfoe as az
+    monkeypatch.setattr(az, "step_polynomial", _az_step_variant(flip=True))
+    assert _fails(pins.check_azrfoe_matches_definition, azfn=az.azrfoe, sizes=(16,))

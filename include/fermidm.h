@@ -9,7 +9,9 @@
  *  - zero temperature (Sec. II.A, D = theta(mu I - Hp)): second-order
  *    projection (SP2) steps X <- X^2 or X <- 2X - X^2, the branch chosen from
  *    traces (Sec. II.B.1, Eq. (1); Tr X^2 = ||X||_F^2 as in Sec. III.B),
- *    started from Gershgorin spectral bounds (Sec. II.C);
+ *    started from Gershgorin spectral bounds (Sec. II.C); or, given bounds
+ *    on the HOMO and LUMO eigenvalues, their shifted and scaled forms
+ *    (A-Z-RFOE, Sec. II.B.2);
  *  - finite temperature (Sec. II.A, D = [exp(beta(Hp - mu I)) + I]^-1): a
  *    doubling recursion of projection maps (Sec. II.B.3, Eq. (2)) that
  *    reproduces the Fermi operator, with mu fixed by Tr D = N_occ;
@@ -81,6 +83,13 @@ typedef struct fdm_options {
                                width, never outside the Gershgorin interval)                  */
     int32_t lanczos_steps;  /* Lanczos steps for bounds = 1 (default 16, at most 64)           */
     int32_t reserved;
+    double homo, lumo;      /* zero T: when homo < lumo, the accelerated expansion (A-Z-RFOE,
+                               Sec. II.B.2): shifted and scaled SP2 polynomials chosen from
+                               these bounds, homo >= the highest occupied eigenvalue and
+                               lumo <= the lowest unoccupied one (e.g. from the previous SCF
+                               step).  Bounds that turn out wrong make the expansion miss
+                               n_occ or stall; the solve then repeats as plain SP2.  NaN
+                               (default) = plain SP2                                           */
     void *workspace;        /* optional caller-owned device memory of workspace_bytes          */
     size_t workspace_bytes; /* at least fdm_workspace_bytes(N, kT, precision)                  */
 } fdm_options;
@@ -108,7 +117,8 @@ typedef struct fdm_stats {
                                    (3x for the split forms, which run three products)          */
     double gersh_min, gersh_max;    /* Gershgorin bounds (e_min / e_max hold the bounds used)  */
     int32_t lanczos_steps;      /* Lanczos steps run for the bounds (0 with bounds = 0)        */
-    int32_t reserved;
+    int32_t accelerated;        /* zero T: 1 = the accelerated expansion gave D; -1 = it was
+                                   tried and missed, and plain SP2 gave D; 0 = plain SP2       */
     double mcweeny_idem[4];     /* zero-T mixed: ||X^2 - X||_F at each FP64 McWeeny check      */
     double mcweeny_trace_err[4];/* zero-T mixed: |Tr X - n_occ| at each FP64 McWeeny check     */
     double mu_hist[16];         /* finite T: mu of the first 16 Fermi-operator evaluations      */

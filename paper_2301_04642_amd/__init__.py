@@ -37,7 +37,8 @@ class fdm_options(ctypes.Structure):
                 ("fd_final_fp64", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("bounds", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("workspace", ctypes.c_void_p),
+                ("reserved", ctypes.c_int32), ("homo", ctypes.c_double),
+                ("lumo", ctypes.c_double), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t)]
 
 
@@ -52,7 +53,7 @@ class fdm_stats(ctypes.Structure):
                 ("band_energy", ctypes.c_double), ("ms_total", ctypes.c_double),
                 ("prod_ms", ctypes.c_double * FDM_NPREC), ("flops", ctypes.c_double * FDM_NPREC),
                 ("gersh_min", ctypes.c_double), ("gersh_max", ctypes.c_double),
-                ("lanczos_steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("lanczos_steps", ctypes.c_int32), ("accelerated", ctypes.c_int32),
                 ("mcweeny_idem", ctypes.c_double * 4), ("mcweeny_trace_err", ctypes.c_double * 4),
                 ("mu_hist", ctypes.c_double * 16), ("mu_trace_err", ctypes.c_double * 16)]
 

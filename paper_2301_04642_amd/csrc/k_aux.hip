@@ -389,6 +389,7 @@ __global__ __launch_bounds__(256) void k_decide(DevState *st, HostMirror *hm,
         case D_SP2: {
             // s0, s1: Tr and ||.||^2 of X_{n+1}; s2 = ||X_n^2 - X_n||^2.
             const int n = st->iter;
+            const int sm = st->switch_mode & 7;   // bit 3: divergence guard
             const double idem = sqrt(s2);
             const double two_back = st->idem_hist[1];  // idempotency of X_{n-2}
             st->idem_hist[0] = st->idem_hist[1];
@@ -400,6 +401,15 @@ __global__ __launch_bounds__(256) void k_decide(DevState *st, HostMirror *hm,
             // iteration sits on its rounding floor.
             const bool stagnant = idem < 0.1 && idem >= 0.8 * two_back;
             const bool advance_bit = true;
+            // X_{n+1} has left [0, 1] (||X||^2 > Tr X needs eigenvalues
+            // outside it; only shifted polynomials built from wrong HOMO/LUMO
+            // bounds can do that): give up before it overflows
+            if ((st->switch_mode & 8) && (!(idem < INFINITY) || !(s1 <= s0 + 0.5))) {
+                st->done = 1;
+                st->result_iter = n;
+                st->status = FDM_ENOCONV;
+                break;
+            }
             // converged: idempotent and holding n_occ electrons (st->trace is
             // still Tr X_n here)
             if (idem <= st->tol && fabs(st->trace - st->n_occ) <= st->tol) {
@@ -407,10 +417,10 @@ __global__ __launch_bounds__(256) void k_decide(DevState *st, HostMirror *hm,
                 st->result_iter = n;
                 break;
             }
-            if (st->switch_mode == 1 && (idem <= st->tau || stagnant)) {
+            if (sm == 1 && (idem <= st->tau || stagnant)) {
                 st->done = 1;
                 st->result_iter = n + 1;
-            } else if (st->switch_mode != 1 && stagnant) {
+            } else if (sm != 1 && stagnant) {
                 st->done = 1;
                 st->result_iter = n;
                 st->status = FDM_ENOCONV;
@@ -426,7 +436,7 @@ __global__ __launch_bounds__(256) void k_decide(DevState *st, HostMirror *hm,
             if (!st->done && st->iter >= st->max_iter) {
                 st->done = 1;
                 st->result_iter = st->iter;
-                if (st->switch_mode == 0) st->status = FDM_ENOCONV;
+                if (sm == 0) st->status = FDM_ENOCONV;
             }
             break;
         }

@@ -353,18 +353,64 @@ int Ctx::run_loop(int max_steps, const std::function<int(int)> &enqueue) {
     return FDM_EHIP;
 }
 
+// Accelerated expansion (A-Z-RFOE, Sec. II.B.2): the unoccupied eigenvalues
+// of X_0 lie in [0, l0], the occupied ones in [h0, 1].  Each step squares the
+// larger of the errors e_u = l and e_o = 1 - h with the parabola's vertex
+// moved to half of it, so the two ends of that interval land on the same
+// value:
+//     e_u >= e_o:  p(x) = k (x - s)^2,          s = e_u / 2
+//     e_u <  e_o:  p(x) = 1 - k (1 - s - x)^2,  s = e_o / 2,  k = 1 / (1 - s)^2
+// (s = 0 gives X^2 and 2X - X^2).  The interval ends' images are the next
+// bounds, so the sequence depends on (l0, h0) only and is fixed up front.
+void Ctx::build_az_schedule(double l, double h, int steps) {
+    az_coef.assign(3 * (size_t)steps, 0.0);
+    az_branch.assign(steps, 0);
+    for (int j = 0; j < steps; ++j) {
+        const double eu = l, eo = 1.0 - h;
+        double *c = &az_coef[3 * (size_t)j];
+        if (eu >= eo) {
+            const double sh = 0.5 * eu, k = 1.0 / ((1.0 - sh) * (1.0 - sh));
+            c[0] = k;
+            c[1] = -2.0 * k * sh;
+            c[2] = k * sh * sh;
+            az_branch[j] = 1;
+            l = k * sh * sh;
+            h = k * (h - sh) * (h - sh);
+        } else {
+            const double sh = 0.5 * eo, k = 1.0 / ((1.0 - sh) * (1.0 - sh)), u = 1.0 - sh;
+            c[0] = -k;
+            c[1] = 2.0 * k * u;
+            c[2] = 1.0 - k * u * u;
+            az_branch[j] = 0;
+            l = 1.0 - k * (u - l) * (u - l);
+            h = 1.0 - k * sh * sh;
+        }
+    }
+}
+
 // SP2 products from X_0 in bufs[0] (its sums already reduced by D_INIT).
+// sched_off >= 0: step k applies the accelerated polynomial sched_off + k;
+// otherwise the device picks X^2 or 2X - X^2 from the traces.
 int Ctx::sp2_phase(int prec, void *b0, void *b1, int max_iter, int switch_mode, double tau,
-                   void **result, int *iters) {
-    int rc = set_params(tau, max_iter, switch_mode, 0);
+                   int sched_off, void **result, int *iters) {
+    // the shifted polynomials can throw a state out of [0, 1] when the HOMO /
+    // LUMO bounds are wrong: the device then ends the phase (bit 3)
+    int rc = set_params(tau, max_iter, switch_mode | (sched_off >= 0 ? 8 : 0), 0);
     if (rc) return rc;
     void *bufs[2] = {b0, b1};
     // sel = 0: 2X - X^2 ;  sel = 1: X^2
     static const double c_sub[3] = {-1.0, 2.0, 0.0};
     static const double c_sq[3] = {1.0, 0.0, 0.0};
     rc = run_loop(max_iter, [&](int k) -> int {
-        int q = product(prec, bufs[k & 1], bufs[k & 1], bufs[k & 1], bufs[(k + 1) & 1], c_sub,
+        int q;
+        if (sched_off >= 0 && !az_branch.empty()) {
+            const size_t j = std::min((size_t)(sched_off + k), az_branch.size() - 1);
+            q = product(prec, bufs[k & 1], bufs[k & 1], bufs[k & 1], bufs[(k + 1) & 1],
+                        &az_coef[3 * j], nullptr, false, true);
+        } else {
+            q = product(prec, bufs[k & 1], bufs[k & 1], bufs[k & 1], bufs[(k + 1) & 1], c_sub,
                         c_sq, true, true);
+        }
         if (q) return q;
         return decide(D_SP2, last_ntiles, 4);
     });
@@ -436,8 +482,18 @@ int Ctx::finish(const double *Hp, int64_t ldh, const void *dm, int dm_f32, doubl
     if (rc) return rc;
     stats.band_energy = h.sums[0];
     stats.trace = h.sums[1];
+    const int sp2_steps = stats.iters_fp64 + stats.iters_fp64_first + stats.iters_low;
     for (int k = 0; k < 4; ++k) {
         stats.branch_bits[k] = h.bits[k];
+        if (!az_branch.empty()) {
+            // the accelerated forms follow the fixed schedule
+            uint64_t b = 0;
+            for (int j = 0; j < 64; ++j) {
+                const int g = 64 * k + j;
+                if (g < sp2_steps && g < (int)az_branch.size() && az_branch[g]) b |= 1ull << j;
+            }
+            stats.branch_bits[k] = b;
+        }
         stats.mcweeny_idem[k] = (k <= stats.mcweeny_steps && stats.mcweeny_steps > 0) ||
                                         (k == 0 && stats.iters_low > 0)
                                     ? h.mcw_idem[k]
@@ -578,7 +634,21 @@ int Ctx::refine_bounds(const double *Hp, int64_t ldh, DevState *h) {
 }
 
 int Ctx::solve_zero_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, double *E_band) {
+    const bool accel = std::isfinite(opt.homo) && std::isfinite(opt.lumo) && opt.lumo > opt.homo;
+    int rc = solve_zero_t_once(Hp, ldh, D, ldd, E_band, accel);
+    if (rc || stats.accelerated != 1 || status == FDM_OK) return rc;
+    // the bounds were wrong (a state on the wrong side never settles): plain SP2
+    status = FDM_OK;
+    rc = solve_zero_t_once(Hp, ldh, D, ldd, E_band, false);
+    stats.accelerated = -1;
+    return rc;
+}
+
+int Ctx::solve_zero_t_once(const double *Hp, int64_t ldh, double *D, int64_t ldd, double *E_band,
+                           bool accel) {
     const int64_t k = (int64_t)llround(n_occ);
+    stats.accelerated = 0;
+    stats.iters_fp64_first = stats.iters_low = stats.iters_fp64 = stats.mcweeny_steps = 0;
     DevState h;
     int rc = bounds(Hp, ldh, &h);
     if (rc) return rc;
@@ -605,6 +675,18 @@ int Ctx::solve_zero_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, dou
     }
     const int prec = opt.precision;
     const int max_iter = opt.max_iter;
+    az_coef.clear();
+    az_branch.clear();
+    if (accel) {
+        const double w = h.emax - h.emin;
+        const double l0 = std::min(std::max((h.emax - opt.lumo) / w, 0.0), 1.0);
+        const double h0 = std::min(std::max((h.emax - opt.homo) / w, 0.0), 1.0);
+        if (l0 < h0) {
+            build_az_schedule(l0, h0, 2 * max_iter + 8);
+            stats.accelerated = 1;
+        }
+    }
+    const int sched = stats.accelerated == 1 ? 0 : -1;
     rc = set_params(0.0, max_iter, 0, 1);
     if (rc) return rc;
     int np = 0;
@@ -620,7 +702,7 @@ int Ctx::solve_zero_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, dou
         if (rc) return rc;
         void *res = nullptr;
         int it = 0;
-        rc = sp2_phase(P_F64, X64[0], X64[1], max_iter, 0, 0.0, &res, &it);
+        rc = sp2_phase(P_F64, X64[0], X64[1], max_iter, 0, 0.0, sched, &res, &it);
         if (rc) return rc;
         stats.iters_fp64 = it;
         stats.idempotency = r->hm_host->idem;
@@ -663,7 +745,7 @@ int Ctx::solve_zero_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, dou
         if (rc) return rc;
         void *res = nullptr;
         int it = 0;
-        rc = sp2_phase(P_F64, X64[0], X64[1], k64, 2, tau, &res, &it);
+        rc = sp2_phase(P_F64, X64[0], X64[1], k64, 2, tau, sched, &res, &it);
         if (rc) return rc;
         stats.iters_fp64_first = it;
         if (r->hm_host->done && r->hm_host->result_iter < k64 && r->hm_host->idem <= tol) {
@@ -683,10 +765,14 @@ int Ctx::solve_zero_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, dou
     rc = decide(D_INIT, np, 4);
     if (rc) return rc;
     int itl = 0;
-    rc = sp2_phase(prec, X32[0], X32[1], max_iter, 1, tau, &cur32, &itl);
+    rc = sp2_phase(prec, X32[0], X32[1], max_iter, 1, tau,
+                   sched < 0 ? -1 : stats.iters_fp64_first, &cur32, &itl);
     if (rc) return rc;
     stats.iters_low = itl;
-    status = 0;  // reaching the cap in the low-precision phase is not an error
+    if (status) {  // the iterate left [0, 1]: report it
+        stats.idempotency = r->hm_host->idem;
+        return finish(Hp, ldh, cur32, 1, D, ldd, E_band);
+    }
     rc = affine(1, cur32, r->lay.ld, 0, X64[0], 1.0, 0.0, 0, &np);
     if (rc) return rc;
     rc = decide(D_INIT, np, 4);
@@ -734,6 +820,8 @@ int fdm_options_default(fdm_options *opt) {
     opt->tile = 0;
     opt->bounds = 1;
     opt->lanczos_steps = 16;
+    opt->homo = NAN;
+    opt->lumo = NAN;
     return FDM_OK;
 }
 

@@ -82,6 +82,10 @@ struct Ctx {
     int used_tile = 0;
     std::vector<int> phase_launches;
     std::vector<double> ritz, ritz_w;  // Lanczos Ritz values and Gauss weights of Hp
+    // accelerated zero-T expansion: coefficients (a, b, c) of a X^2 + b X + c I
+    // for SP2 step k at az_coef[3k..3k+2], and the form (1 = squaring form)
+    std::vector<double> az_coef;
+    std::vector<uint8_t> az_branch;
     std::vector<Timed> timed;
 
     int tile_for(int prec) const;
@@ -94,7 +98,8 @@ struct Ctx {
                double b, int zt, int *nparts);
     int run_loop(int max_steps, const std::function<int(int)> &enqueue);
     int sp2_phase(int prec, void *b0, void *b1, int max_iter, int switch_mode, double tau,
-                  void **result, int *iters);
+                  int sched_off, void **result, int *iters);
+    void build_az_schedule(double l0, double h0, int steps);
     int mcweeny_phase(double *x0, double *t, double *x1, int max_steps, double **result,
                       int *steps);
     int read_state(DevState *out);
@@ -104,6 +109,8 @@ struct Ctx {
                double *E_band);
     int validate_symmetric(const double *Hp, int64_t ldh);
     int solve_zero_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, double *E_band);
+    int solve_zero_t_once(const double *Hp, int64_t ldh, double *D, int64_t ldd, double *E_band,
+                          bool accel);
     int canonical_correction(void *dm, double tr, double trdd, double *mu, void **out);
     int solve_finite_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, double *E_band);
     int fermi_operator(const double *Hp, int64_t ldh, double mu, int depth, int prec,

@@ -1,0 +1,125 @@
+"""Accelerated zero-temperature expansion (A-Z-RFOE, Sec. II.B.2) on the GPU
+against the CPU oracle.
+
+FP64: D equals the oracle's accelerated expansion and the definition to
+1e-10, the polynomial schedule (branch bits) equals the oracle's, and the
+product count matches it.  Mixed forms: the gates of the plain expansion
+(|dE| <= 1e-6 Ha, ||D^2 - D||_F <= 1e-8, |Tr D - n_occ| <= 1e-8) with fewer
+products than plain SP2.  Bounds that are wrong make the device give up and
+the solve repeat as plain SP2 (stats.accelerated = -1), still correct."""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_util import dev, host, reference, say
+
+pytestmark = pytest.mark.gpu
+
+MIXED = ["fp32", "fp16x3", "bf16x3"]
+
+
+@pytest.fixture(scope="module")
+def fdm():
+    import paper_2301_04642_amd as m
+    return m
+
+
+def gap_bounds(wl, shrink=0.0):
+    """HOMO/LUMO bounds from the known spectrum, the gap understated by
+    `shrink` of itself (split evenly)."""
+    lam = np.sort(wl.lam)
+    k = int(round(wl.n_occ))
+    gap = lam[k] - lam[k - 1]
+    return lam[k - 1] + 0.5 * shrink * gap, lam[k] - 0.5 * shrink * gap
+
+
+@pytest.mark.parametrize("n,shrink", [(64, 0.0), (129, 0.4), (300, 0.0), (300, 0.8)])
+def test_fp64_matches_oracle(fdm, n, shrink):
+    from oracle import azrfoe as az
+    from oracle import density as den
+    wl = workloads.config_workload(0, n=n)
+    homo, lumo = gap_bounds(wl, shrink)
+    d_ref, e_ref, _, _ = reference(wl)
+    say("azrfoe fp64", n, shrink)
+    D, e, st = fdm.solve(dev(wl.hp), wl.n_occ, 0.0, 1e-11, "fp64", homo=homo, lumo=lumo)
+    d = host(D)
+    assert st.status == 0 and st.accelerated == 1
+    assert np.linalg.norm(d - d_ref) <= 1e-10
+    assert abs(e - e_ref) <= 1e-10
+    assert abs(np.trace(d) - wl.n_occ) <= 1e-10
+    assert np.array_equal(d, d.T)
+    assert abs(den.band_energy(wl.hp, d) - e) <= 1e-10
+    x, info = az.azrfoe(wl.hp, wl.n_occ, homo, lumo, tol=1e-11, bounds=(st.e_min, st.e_max))
+    assert np.linalg.norm(d - x) <= 1e-10
+    assert abs(st.iters_fp64 - info["iterations"]) <= 1
+    k = min(st.iters_fp64, info["iterations"])
+    assert fdm.branch_list(st)[:k] == info["branches"][:k]
+    # fewer products than plain SP2 on the same matrix
+    _, _, st_plain = fdm.solve(dev(wl.hp), wl.n_occ, 0.0, 1e-11, "fp64")
+    print(f"[report] azrfoe fp64 n={n} shrink={shrink}: {st.iters_fp64} products "
+          f"(oracle {info['iterations']}, plain SP2 {st_plain.iters_fp64})", flush=True)
+    assert st.iters_fp64 < st_plain.iters_fp64
+
+
+@pytest.mark.parametrize("prec", MIXED)
+def test_mixed_bands(fdm, prec):
+    wl = workloads.config_workload(1, n=1000)
+    d_ref, e_ref, _, _ = reference(wl)
+    homo, lumo = gap_bounds(wl, 0.25)
+    say("azrfoe", prec, wl.n)
+    D, e, st = fdm.solve(dev(wl.hp), wl.n_occ, 0.0, wl.tol, prec, homo=homo, lumo=lumo)
+    d = host(D)
+    _, _, st_plain = fdm.solve(dev(wl.hp), wl.n_occ, 0.0, wl.tol, prec)
+    de = abs(e - e_ref)
+    print(f"[report] azrfoe {prec} n={wl.n}: k64={st.iters_fp64_first} low={st.iters_low} "
+          f"mcw={st.mcweeny_steps} |dE|={de:.2e} (plain SP2: k64={st_plain.iters_fp64_first} "
+          f"low={st_plain.iters_low} mcw={st_plain.mcweeny_steps})", flush=True)
+    assert st.status == 0 and st.accelerated == 1
+    assert de <= 1e-6
+    assert np.linalg.norm(d @ d - d) <= 1e-8
+    assert abs(np.trace(d) - wl.n_occ) <= 1e-8
+    assert np.array_equal(d, d.T)
+    assert (st.iters_fp64_first + st.iters_low) < (st_plain.iters_fp64_first + st_plain.iters_low)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_wrong_bounds_fall_back(fdm, prec):
+    """HOMO bound 0.3 Ha below the HOMO and LUMO bound 0.3 Ha above the LUMO:
+    the accelerated polynomials throw states out of [0, 1]; the device ends
+    that phase and the solve repeats as plain SP2."""
+    wl = workloads.config_workload(0, n=256)
+    d_ref, e_ref, _, _ = reference(wl)
+    homo, lumo = gap_bounds(wl)
+    say("azrfoe wrong bounds", prec)
+    D, e, st = fdm.solve(dev(wl.hp), wl.n_occ, 0.0, 1e-10, prec, homo=homo - 0.3,
+                         lumo=lumo + 0.3)
+    d = host(D)
+    assert st.status == 0 and st.accelerated == -1
+    assert abs(e - e_ref) <= (1e-10 if prec == "fp64" else 1e-6)
+    assert abs(np.trace(d) - wl.n_occ) <= 1e-8
+
+
+def test_config1_full_size(fdm):
+    """N = 4000 band workload, FP64 and FP32 with bounds that understate the
+    gap by 25%: same gates as the plain forms, about half the products."""
+    wl = workloads.config_workload(1)
+    homo, lumo = gap_bounds(wl, 0.25)
+    from oracle import density as den
+    f, _ = den.occupations(wl.lam, wl.n_occ, 0.0)
+    e_ref = float(np.dot(f, wl.lam))
+    H = dev(wl.hp)
+    for prec in ("fp64", "fp32"):
+        say("azrfoe config1", prec)
+        D, e, st = fdm.solve(H, wl.n_occ, 0.0, wl.tol, prec, homo=homo, lumo=lumo)
+        _, _, stp = fdm.solve(H, wl.n_occ, 0.0, wl.tol, prec)
+        d = host(D)
+        rows = np.random.default_rng(3).choice(wl.n, 4, replace=False)
+        idem_rows = np.linalg.norm(d[rows] @ d - d[rows])
+        print(f"[report] azrfoe config1 {prec}: products {sum(st.products)} "
+              f"(plain {sum(stp.products)}) |dE|={abs(e - e_ref):.2e} "
+              f"|dTr|={abs(np.trace(d) - wl.n_occ):.2e} rows idem={idem_rows:.1e}", flush=True)
+        assert st.status == 0 and st.accelerated == 1
+        assert abs(e - e_ref) <= (1e-9 if prec == "fp64" else 1e-6)
+        assert abs(np.trace(d) - wl.n_occ) <= 1e-8
+        assert idem_rows <= 1e-8
+        assert sum(st.products) < 0.8 * sum(stp.products)

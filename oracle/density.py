@@ -142,12 +142,18 @@ def banded_eigenvalues(h: np.ndarray, bandwidth: int) -> np.ndarray:
     beyond `bandwidth` diagonals, by LAPACK's banded symmetric eigensolver
     (a library routine); used for the paper's synthetic matrix, whose
     entries decay like exp(-0.5 |i - j|)."""
-    from scipy.linalg import eig_banded
     n = h.shape[0]
     bw = min(bandwidth, n - 1)
     ab = np.zeros((bw + 1, n))
     for d in range(bw + 1):
         ab[bw - d, d:] = np.diag(h, d)
+    return band_storage_eigenvalues(ab)
+
+
+def band_storage_eigenvalues(ab: np.ndarray) -> np.ndarray:
+    """Eigenvalues (ascending) of the symmetric matrix held in LAPACK upper
+    band storage ab[bw - d, j] = H[j - d, j], by the banded eigensolver."""
+    from scipy.linalg import eig_banded
     return np.sort(eig_banded(ab, lower=False, eigvals_only=True))
 
 

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle import density as den  # noqa: E402
-from workloads import paper_e1_matrix  # noqa: E402
+from workloads import paper_e1_band, paper_e1_matrix  # noqa: E402
 
 
 def write(name, header, rows):
@@ -42,5 +42,27 @@ def main():
           [("mu", mu), ("band_energy", e), ("d_diag", np.diag(d)), ("d_row0", d[0])])
 
 
+def large(n):
+    """The paper's matrix at one of its sizes (Sec. IV): reference energies
+    from the banded eigensolver on the band storage (entries beyond 80
+    diagonals are below exp(-40))."""
+    lam = den.band_storage_eigenvalues(paper_e1_band(n, 80))
+    k = int(0.9 * n)
+    e0, _, _ = den.reference_energy(lam, k, 0.0)
+    e1, mu, _ = den.reference_energy(lam, 0.85 * n, 0.0016)
+    write(f"e1_n{n}.txt",
+          [f"Paper's synthetic Hp (Sec. IV), N = {n}: H_ij = exp(-0.5|i-j|) sin(min(i,j)+1)",
+           f"zero temperature: N_occ = {k} (90%); finite temperature: N_occ = {0.85 * n} (85%), "
+           "kT = 0.0016 Ha",
+           "written by tests/golden/make_golden.py --large from the oracle (banded eigensolver)"],
+          [("n", n), ("lambda_min_max", [lam[0], lam[-1]]), ("zero_t_n_occ", k),
+           ("homo_lumo", [lam[k - 1], lam[k]]), ("zero_t_band_energy", e0),
+           ("finite_t_mu", mu), ("finite_t_band_energy", e1)])
+
+
 if __name__ == "__main__":
-    main()
+    if "--large" in sys.argv:
+        for n in (16384, 32768):
+            large(n)
+    else:
+        main()

@@ -15,7 +15,9 @@ from .gen import (  # noqa: F401
     make_workload,
     config_workload,
     serving_requests,
+    paper_e1_band,
     paper_e1_matrix,
+    paper_e1_rows,
     serving_workload,
     CONFIGS,
 )

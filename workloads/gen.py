@@ -237,3 +237,23 @@ def paper_e1_matrix(n: int) -> np.ndarray:
     i = np.arange(n)
     lo = np.minimum(i[:, None], i[None, :])
     return np.exp(-0.5 * np.abs(i[:, None] - i[None, :])) * np.sin(lo + 1.0)
+
+
+def paper_e1_band(n: int, bandwidth: int = 80) -> np.ndarray:
+    """The paper's matrix (see paper_e1_matrix) in LAPACK upper band storage:
+    ab[bandwidth - d, j] = H[j - d, j] for d = 0..bandwidth (entries further
+    out are below exp(-40) and left out)."""
+    bw = min(bandwidth, n - 1)
+    ab = np.zeros((bw + 1, n))
+    for d in range(bw + 1):
+        j = np.arange(d, n)
+        ab[bw - d, d:] = np.exp(-0.5 * np.abs(float(d))) * np.sin(np.minimum(j - d, j) + 1.0)
+    return ab
+
+
+def paper_e1_rows(n: int, r0: int, r1: int) -> np.ndarray:
+    """Rows r0..r1-1 of paper_e1_matrix(n) (same arithmetic, so large matrices
+    can be built a block of rows at a time)."""
+    i = np.arange(r0, r1)[:, None]
+    j = np.arange(n)[None, :]
+    return np.exp(-0.5 * np.abs(i - j)) * np.sin(np.minimum(i, j) + 1.0)

@@ -124,6 +124,10 @@ typedef struct fdm_stats {
     double mu_hist[16];         /* finite T: mu of the first 16 Fermi-operator evaluations      */
     double mu_trace_err[16];    /* finite T: Tr D(mu) - n_occ at those evaluations (their own   */
                                 /*   precision); mu_evals says how many entries are valid       */
+    int32_t fallback_fp64;      /* zero T mixed: 1 = the low-precision phase ran out of steps
+                                   without reaching tau (rounding noise above the gap of X), and
+                                   the solve was repeated in FP64                              */
+    int32_t reserved2;
 } fdm_stats;
 
 /* Fills *opt with the defaults listed above.  Returns FDM_EINVAL if opt is NULL. */

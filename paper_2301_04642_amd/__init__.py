@@ -1,7 +1,7 @@
 """Python binding of libfermidm (MI355X / gfx950 density-matrix library).
 
 Argument marshalling only: every step runs in the HIP library built from
-``csrc/`` (``python -m paper_2301_04642_amd.build``).  PyTorch provides device
+``csrc/`` (``python paper_2301_04642_amd/build.py``).  PyTorch provides device
 memory and the current stream.  Importing this module fails loudly when the
 library has not been built; there is no CPU fallback.
 
@@ -55,7 +55,8 @@ class fdm_stats(ctypes.Structure):
                 ("gersh_min", ctypes.c_double), ("gersh_max", ctypes.c_double),
                 ("lanczos_steps", ctypes.c_int32), ("accelerated", ctypes.c_int32),
                 ("mcweeny_idem", ctypes.c_double * 4), ("mcweeny_trace_err", ctypes.c_double * 4),
-                ("mu_hist", ctypes.c_double * 16), ("mu_trace_err", ctypes.c_double * 16)]
+                ("mu_hist", ctypes.c_double * 16), ("mu_trace_err", ctypes.c_double * 16),
+                ("fallback_fp64", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
     def as_dict(self):
         d = {}
@@ -81,7 +82,7 @@ class FdmError(RuntimeError):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2301_04642_amd.build`")
+        raise ImportError(f"{LIB_PATH} is not built; run `python paper_2301_04642_amd/build.py`")
     # PyTorch bundles its own HIP runtime with the same soname as the system
     # one.  Load torch's first so that libfermidm binds to it: one HIP runtime
     # (and one HSA runtime) per process, shared device memory and streams.

@@ -1,6 +1,6 @@
 """Builds libfermidm.so (gfx950) in place from csrc/ with hipcc.
 
-    python -m paper_2301_04642_amd.build
+    python paper_2301_04642_amd/build.py
 """
 import os
 import subprocess

@@ -275,7 +275,7 @@ void k_symprod(ProdArgs a) {
     const int w = tid >> 6, lane = tid & 63;
     const int wr = w >> 1, wc = w & 1, lr = lane & 15, lg = lane >> 4;
     // FP32-accumulating forms sum each K stage in a fresh accumulator and
-    // fold it into the running sum with a compensated (two-sum) add: the
+    // fold it into the running sum with a compensated (Kahan) add: the
     // accumulation error then grows with the stage length (32) instead of
     // with N, which lowers the rounding floor of the low-precision SP2
     // iterates ~30x (the operand rounding is what remains).
@@ -342,11 +342,12 @@ void k_symprod(ProdArgs a) {
     };
 
     // Stage kt lives in LDS buffer kt & 1; the loop is unrolled by two so
-    // buffer and register-set indices are static.  The split forms prefetch
-    // two stages ahead (register set kt & 1 carries stage kt); FP64 / FP32
-    // carry 4x more MFMA cycles per stage and prefetch one stage ahead.
+    // buffer and register-set indices are static.  The split forms and FP32
+    // prefetch two stages ahead (register set kt & 1 carries stage kt; 1%
+    // faster for FP32 at N = 4000 and 16000); FP64 has no registers left
+    // for the second set and prefetches one stage ahead.
     const int nk = a.kext / KST;
-    if constexpr (SPLIT) {
+    if constexpr (SPLIT || P == P_F32) {
         gload(0, ga0, gb0);
         if (nk > 1) gload(1, ga1, gb1);
         lstore(0, ga0, gb0);

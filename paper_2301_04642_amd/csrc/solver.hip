@@ -213,11 +213,14 @@ Resources *thread_resources(int dev) {
 int Ctx::tile_for(int prec) const {
     if (opt.tile == 64 || opt.tile == 128) return opt.tile;
     // Measured on MI355X (N = 4000 / 16000): FP64 and FP32 are fastest with
-    // 64-wide tiles at every size (4 blocks per CU hide the MFMA latency; the
-    // FP32 tiles also carry the compensated accumulation); the 16-bit forms
-    // gain from 128-wide tiles (half the panel traffic per flop) once there
-    // are enough of them to fill the 256 CUs several times.
-    if (prec == P_F64 || prec == P_F32) return 64;
+    // 64-wide tiles at every size (4 blocks per CU hide the MFMA latency).
+    // The split forms need the compensated accumulation of the 64-wide tiles
+    // at large N: with uncompensated 128-wide tiles (10% faster products at
+    // N = 16000) the FP16x3 iterate of the paper's N = 32768 matrix never got
+    // below tau in 100 steps (|dE| 4.5e-5 Ha), and N = 30000 ended at |dE|
+    // 1.4e-7 instead of 2.6e-10.  The single-pass 16-bit forms (reported,
+    // not gated) take 128-wide tiles once there are enough to fill the chip.
+    if (prec != P_F16 && prec != P_BF16) return 64;
     const int64_t t128 = ntiles_for(n, 128);
     return (t128 >= 4 * 256) ? 128 : 64;
 }
@@ -636,11 +639,26 @@ int Ctx::refine_bounds(const double *Hp, int64_t ldh, DevState *h) {
 int Ctx::solve_zero_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, double *E_band) {
     const bool accel = std::isfinite(opt.homo) && std::isfinite(opt.lumo) && opt.lumo > opt.homo;
     int rc = solve_zero_t_once(Hp, ldh, D, ldd, E_band, accel);
-    if (rc || stats.accelerated != 1 || status == FDM_OK) return rc;
-    // the bounds were wrong (a state on the wrong side never settles): plain SP2
-    status = FDM_OK;
-    rc = solve_zero_t_once(Hp, ldh, D, ldd, E_band, false);
-    stats.accelerated = -1;
+    if (rc) return rc;
+    if (stats.accelerated == 1 && status != FDM_OK) {
+        // the bounds were wrong (a state on the wrong side never settles): plain SP2
+        status = FDM_OK;
+        rc = solve_zero_t_once(Hp, ldh, D, ldd, E_band, false);
+        if (rc) return rc;
+        stats.accelerated = -1;
+    }
+    if (low_cap) {
+        // The low-precision phase used all its steps without reaching tau:
+        // its rounding noise is above the HOMO-LUMO gap of X, and the
+        // subspace it leaves cannot be trusted.  Solve again in FP64.
+        const int keep_prec = opt.precision, keep_acc = stats.accelerated;
+        opt.precision = P_F64;
+        status = FDM_OK;
+        rc = solve_zero_t_once(Hp, ldh, D, ldd, E_band, accel && keep_acc == 1);
+        opt.precision = keep_prec;
+        if (keep_acc == -1) stats.accelerated = -1;
+        stats.fallback_fp64 = 1;
+    }
     return rc;
 }
 
@@ -649,6 +667,7 @@ int Ctx::solve_zero_t_once(const double *Hp, int64_t ldh, double *D, int64_t ldd
     const int64_t k = (int64_t)llround(n_occ);
     stats.accelerated = 0;
     stats.iters_fp64_first = stats.iters_low = stats.iters_fp64 = stats.mcweeny_steps = 0;
+    low_cap = false;
     DevState h;
     int rc = bounds(Hp, ldh, &h);
     if (rc) return rc;
@@ -772,6 +791,10 @@ int Ctx::solve_zero_t_once(const double *Hp, int64_t ldh, double *D, int64_t ldd
     if (status) {  // the iterate left [0, 1]: report it
         stats.idempotency = r->hm_host->idem;
         return finish(Hp, ldh, cur32, 1, D, ldd, E_band);
+    }
+    if (itl >= max_iter && r->hm_host->idem > tau) {
+        low_cap = true;
+        return FDM_OK;
     }
     rc = affine(1, cur32, r->lay.ld, 0, X64[0], 1.0, 0.0, 0, &np);
     if (rc) return rc;

@@ -78,6 +78,7 @@ struct Ctx {
     double n_occ = 0.0, tol = 0.0, kT = 0.0;
     int status = 0;
     int split_prec = -1;  // split precision whose operand companions are kept
+    bool low_cap = false; // the low-precision SP2 phase ran out of steps above tau
     int last_ntiles = 0;
     int used_tile = 0;
     std::vector<int> phase_launches;

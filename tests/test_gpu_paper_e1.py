@@ -71,3 +71,70 @@ def test_e1_finite_t(fdm, e1, prec):
     assert st.status == 0
     assert abs(np.trace(d) - n_occ) <= 1e-8
     assert abs(e - e_ref) <= (1e-9 if prec == "fp64" else 1e-6)
+
+
+# ---------------------------------------------------------------------------
+# the paper's larger sizes (Sec. IV): reference values from the golden files
+# written by tests/golden/make_golden.py --large (banded eigensolver)
+# ---------------------------------------------------------------------------
+
+def golden(n):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", f"e1_n{n}.txt")
+    vals = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, *v = line.split()
+        vals[k] = [float(x) for x in v]
+    return vals
+
+
+def e1_device(n, block=2048):
+    """The paper's matrix built on the device a block of rows at a time
+    (torch elementwise exp/sin; same formula as workloads.paper_e1_rows)."""
+    import torch
+    H = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    j = torch.arange(n, device="cuda", dtype=torch.float64)[None, :]
+    for r0 in range(0, n, block):
+        i = torch.arange(r0, min(n, r0 + block), device="cuda", dtype=torch.float64)[:, None]
+        H[r0:r0 + i.shape[0]] = torch.exp(-0.5 * (i - j).abs()) * torch.sin(torch.minimum(i, j) + 1.0)
+    return H
+
+
+@pytest.mark.parametrize("n", [16384, 32768])
+def test_e1_paper_sizes_zero_t(fdm, n):
+    import torch
+    g = golden(n)
+    n_occ = int(g["zero_t_n_occ"][0])
+    e_ref = g["zero_t_band_energy"][0]
+    homo, lumo = g["homo_lumo"]
+    say("E1 build", n)
+    H = e1_device(n)
+    rows = np.sort(np.random.default_rng(n).choice(n, 3, replace=False))
+    ref_rows = workloads.paper_e1_rows(n, 0, 1)
+    assert np.allclose(host(H[:1]), ref_rows, rtol=1e-15, atol=1e-16)
+    for r in rows:
+        assert np.allclose(host(H[r:r + 1]), workloads.paper_e1_rows(n, r, r + 1),
+                           rtol=1e-15, atol=1e-16)
+    gap = lumo - homo
+    forms = [("fp64", {}), ("fp16x3", {}),
+             ("fp16x3", dict(homo=homo + 0.125 * gap, lumo=lumo - 0.125 * gap))]
+    for prec, extra in forms:
+        say("E1 zero-T", n, prec, "az" if extra else "")
+        D, e, st = fdm.solve(H, n_occ, 0.0, 1e-8, prec, **extra)
+        tr = float(torch.trace(D))
+        dr = D[torch.from_numpy(rows).cuda()]
+        idem_rows = float(torch.linalg.norm(dr @ D - dr))
+        print(f"[report] E1 N={n} {prec}{' A-Z' if extra else ''}: iters "
+              f"{st.iters_fp64}/{st.iters_fp64_first}/{st.iters_low}/mcw{st.mcweeny_steps} "
+              f"products {sum(st.products)} |dE|={abs(e - e_ref):.2e} |dTr|={abs(tr - n_occ):.2e} "
+              f"idem={st.idempotency:.1e} rows idem={idem_rows:.1e} fallback={st.fallback_fp64} "
+              f"{st.ms_total:.0f} ms", flush=True)
+        assert st.status == 0
+        assert st.accelerated == (1 if extra else 0)
+        assert abs(tr - n_occ) <= 1e-8
+        assert st.idempotency <= 1e-8 and idem_rows <= 1e-8
+        assert abs(e - e_ref) <= (1e-8 if prec == "fp64" else 1e-6)
+        del D
+    torch.cuda.empty_cache()

@@ -217,3 +217,15 @@ def test_config1_full_size(fdm, config1, prec):
     else:
         check_mixed(fdm, config1, prec, bounds=0)
         check_mixed(fdm, config1, prec, bounds=1)
+
+
+def test_low_precision_cap_falls_back_to_fp64(fdm):
+    """A low-precision phase that runs out of steps above tau hands the solve
+    to FP64 from the start (here the step cap is too small for either, so the
+    FP64 pass reports ENOCONV after the fallback)."""
+    wl = workloads.config_workload(0)
+    D, e, st = fdm.solve(dev(wl.hp), wl.n_occ, 0.0, 1e-10, "fp32", raise_on_error=False,
+                         max_iter=8, k64=0)
+    assert st.fallback_fp64 == 1
+    assert st.iters_fp64 == 8 and st.status == fdm.FDM_ENOCONV
+    assert st.products[fdm.FDM_FP32] >= 8 and st.products[fdm.FDM_FP64] >= 8

@@ -76,10 +76,13 @@ struct ProdArgs {
     const int32_t *done;    // nullable: exit at once if *done != 0
     double *partials;       // [ntiles][4]
     // Split forms: hi/lo 16-bit companions of A, B (read as operands) and C
-    // (written by the epilogue); lo = hi + hl_off elements.
+    // (written by the epilogue), interleaved per 32 columns: row r of a
+    // companion matrix holds 2*ld values; columns 32c..32c+31 sit at
+    // [64c, 64c + 32) (hi) and [64c + 32, 64c + 64) (lo), so one K stage of
+    // one row is a single 128-byte line.
     const uint16_t *Ahl, *Bhl;
     uint16_t *Chl;
-    int64_t hl_off;
+    int64_t hl_off;         // unused (0)
 };
 
 // ---- launchers (k_symprod.hip, k_aux.hip) --------------------------------
@@ -119,8 +122,9 @@ hipError_t launch_lanczos(const double *H, int64_t ldh, int n, int np, int k, do
 hipError_t launch_set_bounds(DevState *st, double emin, double emax, hipStream_t s);
 
 // hi/lo 16-bit companions of an FP32 working matrix (split precisions):
-// hi = rn(s x), lo = rn(s x - hi), s = 2^12 for FP16, 1 for BF16.
-hipError_t launch_split(int prec, const float *x, uint16_t *hl, int64_t hl_off, int64_t count,
+// hi = rn(s x), lo = rn(s x - hi), s = 2^12 for FP16, 1 for BF16, in the
+// interleaved layout of ProdArgs; x is rows x ld (ld a multiple of 32).
+hipError_t launch_split(int prec, const float *x, uint16_t *hl, int64_t ld, int64_t rows,
                         hipStream_t s);
 
 hipError_t launch_set_params(DevState *st, double n_occ, double tol, double tau, int max_iter,

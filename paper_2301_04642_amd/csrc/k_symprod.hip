@@ -24,8 +24,9 @@
 //    4 v_mfma_f32_16x16x4, FP16/BF16 one v_mfma_f32_16x16x32.
 //  * Split forms keep an FP32 master matrix (epilogue operand, sums) and
 //    16-bit hi/lo companions written once by the producer:
-//    hi = round(s*x), lo = round(s*x - hi) (s = 2^12 for FP16, 1 for BF16);
-//    the operand stages copy the companions straight into LDS and
+//    hi = round(s*x), lo = round(s*x - hi) (s = 2^12 for FP16, 1 for BF16),
+//    interleaved per 32 columns so that one K stage of one row is a single
+//    128-byte line; the operand stages copy them straight into LDS and
 //    AB ~ (hi hi + hi lo + lo hi) / s^2 with FP32 accumulation.
 //  * Workgroups go round-robin over the 8 XCDs; the block index is remapped
 //    so each XCD works on a contiguous run of the tile list (shared row
@@ -139,18 +140,25 @@ __device__ __forceinline__ void split1(float x, uint16_t &hi, uint16_t &lo) {
     }
 }
 
+// Index of the hi value of (row, col) in the interleaved companion layout
+// (lo is 32 further on).
+__device__ __forceinline__ int64_t hl_index(int64_t row, int64_t col, int64_t ld) {
+    return row * 2 * ld + (col >> 5) * 64 + (col & 31);
+}
+
 // hi/lo companions of an FP32 working matrix (elementwise, whole padded area)
 template <int P>
 __global__ __launch_bounds__(256) void k_split(const float *__restrict__ x,
-                                               uint16_t *__restrict__ hl, int64_t hl_off,
+                                               uint16_t *__restrict__ hl, int64_t ld,
                                                int64_t count) {
     const int64_t i4 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
     if (i4 >= count) return;
     const u4_t raw = *(const u4_t *)(x + i4);
     u2_t h, l;
     to_halves<P>(raw, h, l);
-    *(u2_t *)(hl + i4) = h;
-    *(u2_t *)(hl + hl_off + i4) = l;
+    const int64_t k = hl_index(i4 / ld, i4 % ld, ld);
+    *(u2_t *)(hl + k) = h;
+    *(u2_t *)(hl + k + 32) = l;
 }
 
 template <int P>
@@ -237,10 +245,11 @@ void k_symprod(ProdArgs a) {
             const int c = tid + 256 * u;
             const int r = c >> 3, ch = c & 7;
             if constexpr (SPLIT) {
-                // 16-byte chunks 0-3 of a row stage are hi halves, 4-7 lo halves
-                const int64_t off = (ch >> 2) * a.hl_off + k0 + (ch & 3) * 8;
-                ga[u] = *(const u4_t *)(Ahl + (row0 + r) * ld + off);
-                gb[u] = *(const u4_t *)(Bhl + (col0 + r) * ld + off);
+                // one 128-byte line per row stage: 16-byte chunks 0-3 hold the
+                // hi halves, 4-7 the lo halves (k0 = 32 kt)
+                const int64_t off = (int64_t)kt * 64 + ch * 8;
+                ga[u] = *(const u4_t *)(Ahl + (row0 + r) * 2 * ld + off);
+                gb[u] = *(const u4_t *)(Bhl + (col0 + r) * 2 * ld + off);
             } else {
                 ga[u] = *(const u4_t *)(A + (row0 + r) * ld + k0 + ch * EPC);
                 gb[u] = *(const u4_t *)(B + (col0 + r) * ld + k0 + ch * EPC);
@@ -419,11 +428,13 @@ void k_symprod(ProdArgs a) {
                     if constexpr (SPLIT) {
                         uint16_t h, l;
                         split1<P>((float)os, h, l);
-                        a.Chl[row * ld + col] = h;
-                        a.Chl[a.hl_off + row * ld + col] = l;
+                        const int64_t k = hl_index(row, col, ld);
+                        a.Chl[k] = h;
+                        a.Chl[k + 32] = l;
                         if (diag && row < col) {
-                            a.Chl[col * ld + row] = h;
-                            a.Chl[a.hl_off + col * ld + row] = l;
+                            const int64_t km = hl_index(col, row, ld);
+                            a.Chl[km] = h;
+                            a.Chl[km + 32] = l;
                         }
                     }
                     const double od = (double)os;
@@ -441,9 +452,9 @@ void k_symprod(ProdArgs a) {
                         to_halves<P>(bitcast<u4_t>(f4_t{(float)ov[0], (float)ov[1], (float)ov[2],
                                                         (float)ov[3]}),
                                      hi4, lo4);
-                        const int64_t m = col * ld + rb + 4 * lg;
+                        const int64_t m = hl_index(col, rb + 4 * lg, ld);
                         *(u2_t *)(a.Chl + m) = hi4;
-                        *(u2_t *)(a.Chl + a.hl_off + m) = lo4;
+                        *(u2_t *)(a.Chl + m + 32) = lo4;
                     }
                 } else {
 #pragma unroll
@@ -488,16 +499,18 @@ hipError_t launch_p(int bt, const ProdArgs &a, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_split(int prec, const float *x, uint16_t *hl, int64_t hl_off, int64_t count,
+hipError_t launch_split(int prec, const float *x, uint16_t *hl, int64_t ld, int64_t rows,
                         hipStream_t s) {
-    if (count % 4) return hipErrorInvalidValue;
+    if (ld % 32 || rows < 0) return hipErrorInvalidValue;
+    const int64_t count = ld * rows;
     const int64_t nb = (count / 4 + 255) / 256;
+    if (nb == 0) return hipSuccess;
     if (prec == P_F16X3)
-        hipLaunchKernelGGL((k_split<P_F16X3>), dim3((unsigned)nb), dim3(256), 0, s, x, hl, hl_off,
+        hipLaunchKernelGGL((k_split<P_F16X3>), dim3((unsigned)nb), dim3(256), 0, s, x, hl, ld,
                            count);
     else if (prec == P_BF16X3)
-        hipLaunchKernelGGL((k_split<P_BF16X3>), dim3((unsigned)nb), dim3(256), 0, s, x, hl,
-                           hl_off, count);
+        hipLaunchKernelGGL((k_split<P_BF16X3>), dim3((unsigned)nb), dim3(256), 0, s, x, hl, ld,
+                           count);
     else
         return hipSuccess;
     return hipGetLastError();

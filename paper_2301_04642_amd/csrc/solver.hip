@@ -257,7 +257,7 @@ int Ctx::product(int prec, const void *A, const void *B, const void *E, void *C,
         a.Ahl = comp(A);
         a.Bhl = comp(B);
         a.Chl = comp(C);
-        a.hl_off = (int64_t)m;
+        a.hl_off = 0;
         if (!a.Ahl || !a.Bhl || !a.Chl) {
             set_error("internal: split operand outside the FP32 working buffers");
             return FDM_EHIP;
@@ -323,7 +323,7 @@ int Ctx::affine(int in_f32, const void *in, int64_t ldi, int out_f32, void *out,
         const float *f = (const float *)out;
         if (f >= r->x32 && f < r->x32 + (size_t)r->lay.n32 * m) {
             const size_t i = (size_t)(f - r->x32) / m;
-            e = launch_split(split_prec, f, r->x16 + i * 2 * m, (int64_t)m, (int64_t)m, s);
+            e = launch_split(split_prec, f, r->x16 + i * 2 * m, r->lay.ld, r->lay.np, s);
             if (e != hipSuccess) return hip_fail(e, "split launch");
         }
     }

@@ -82,7 +82,10 @@ typedef struct fdm_options {
                                (Ritz values widened by their residual bounds and 1% of the
                                width, never outside the Gershgorin interval)                  */
     int32_t lanczos_steps;  /* Lanczos steps for bounds = 1 (default 16, at most 64)           */
-    int32_t reserved;
+    int32_t estimate_gap;   /* zero T: 1 = after the solve, estimate bounds on the HOMO and LUMO
+                               eigenvalues for a later accelerated solve (stats homo_ub /
+                               lumo_lb; 40 projected Lanczos steps, 4 x 40 matrix-vector
+                               products with Hp and D) (0)                                     */
     double homo, lumo;      /* zero T: when homo < lumo, the accelerated expansion (A-Z-RFOE,
                                Sec. II.B.2): shifted and scaled SP2 polynomials chosen from
                                these bounds, homo >= the highest occupied eigenvalue and
@@ -128,6 +131,11 @@ typedef struct fdm_stats {
                                    without reaching tau (rounding noise above the gap of X), and
                                    the solve was repeated in FP64                              */
     int32_t reserved2;
+    double homo_ub, lumo_lb;    /* zero T with estimate_gap = 1: estimated bounds on the HOMO
+                                   and LUMO eigenvalues (Ritz values of Hp on the occupied and
+                                   unoccupied subspaces of D, widened by their residual
+                                   bounds) to pass as homo / lumo to a later solve; NaN when
+                                   not asked for or when they do not separate                 */
 } fdm_stats;
 
 /* Fills *opt with the defaults listed above.  Returns FDM_EINVAL if opt is NULL. */

@@ -37,7 +37,7 @@ class fdm_options(ctypes.Structure):
                 ("fd_final_fp64", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("bounds", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("homo", ctypes.c_double),
+                ("estimate_gap", ctypes.c_int32), ("homo", ctypes.c_double),
                 ("lumo", ctypes.c_double), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t)]
 
@@ -56,7 +56,8 @@ class fdm_stats(ctypes.Structure):
                 ("lanczos_steps", ctypes.c_int32), ("accelerated", ctypes.c_int32),
                 ("mcweeny_idem", ctypes.c_double * 4), ("mcweeny_trace_err", ctypes.c_double * 4),
                 ("mu_hist", ctypes.c_double * 16), ("mu_trace_err", ctypes.c_double * 16),
-                ("fallback_fp64", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+                ("fallback_fp64", ctypes.c_int32), ("reserved2", ctypes.c_int32),
+                ("homo_ub", ctypes.c_double), ("lumo_lb", ctypes.c_double)]
 
     def as_dict(self):
         d = {}

@@ -119,6 +119,12 @@ hipError_t launch_axpby2(int f32, const void *X, const void *Y, void *out, int64
 
 hipError_t launch_lanczos(const double *H, int64_t ldh, int n, int np, int k, double *v,
                           double *ab, hipStream_t s);
+// k Lanczos steps on the projection of H - sigma I onto range(D) (unocc = 0)
+// or onto range(I - D) (unocc = 1), D a density matrix: v holds 5 vectors
+// of stride np, ab receives alpha[0..k) then beta[0..k).
+hipError_t launch_lanczos_proj(const double *H, int64_t ldh, const double *D, int64_t ldd, int n,
+                               int np, int k, int unocc, double sigma, double *v, double *ab,
+                               hipStream_t s);
 hipError_t launch_set_bounds(DevState *st, double emin, double emax, hipStream_t s);
 
 // hi/lo 16-bit companions of an FP32 working matrix (split precisions):

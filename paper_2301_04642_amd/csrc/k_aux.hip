@@ -230,9 +230,12 @@ __global__ __launch_bounds__(1024) void k_lanczos_start(double *__restrict__ v, 
     for (int i = threadIdx.x; i < n; i += 1024) v[i] *= inv;
 }
 
-// w = H v - beta_prev v_prev, one wave per row of the caller's H.
+// w = a (M v) - shift v + b y - beta_prev v_prev (y, beta_prev nullable),
+// one wave per row of the caller's M.
 __global__ __launch_bounds__(256) void k_lanczos_matvec(const double *__restrict__ H, int64_t ldh,
                                                         int n, const double *__restrict__ v,
+                                                        double a, double shift,
+                                                        const double *__restrict__ y, double b,
                                                         const double *__restrict__ vprev,
                                                         const double *beta_prev,
                                                         double *__restrict__ w) {
@@ -243,7 +246,12 @@ __global__ __launch_bounds__(256) void k_lanczos_matvec(const double *__restrict
     double s = 0.0;
     for (int j = lane; j < n; j += 64) s += h[j] * v[j];
     s = wave_sum(s);
-    if (lane == 0) w[row] = s - (beta_prev ? *beta_prev * vprev[row] : 0.0);
+    if (lane == 0) {
+        double o = a * s - shift * v[row];
+        if (y) o += b * y[row];
+        if (beta_prev) o -= *beta_prev * vprev[row];
+        w[row] = o;
+    }
 }
 
 // alpha = w.v ; w -= alpha v ; beta = ||w|| ; w <- w / beta (single block,
@@ -584,8 +592,38 @@ hipError_t launch_lanczos(const double *H, int64_t ldh, int n, int np, int k, do
         double *vj = v + (size_t)(j % 3) * np;
         double *vp = v + (size_t)((j + 2) % 3) * np;
         double *vn = v + (size_t)((j + 1) % 3) * np;
-        hipLaunchKernelGGL(k_lanczos_matvec, dim3(nb), dim3(256), 0, s, H, ldh, n, vj, vp,
+        hipLaunchKernelGGL(k_lanczos_matvec, dim3(nb), dim3(256), 0, s, H, ldh, n, vj, 1.0, 0.0,
+                           (const double *)nullptr, 0.0, vp,
                            j ? ab + k + j - 1 : (const double *)nullptr, vn);
+        hipLaunchKernelGGL(k_lanczos_update, dim3(1), dim3(1024), 0, s, vn, vj, n, ab + j,
+                           ab + k + j);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_lanczos_proj(const double *H, int64_t ldh, const double *D, int64_t ldd, int n,
+                               int np, int k, int unocc, double sigma, double *v, double *ab,
+                               hipStream_t s) {
+    double *t = v + 3 * (size_t)np, *zero = v + 4 * (size_t)np;
+    hipError_t e = hipMemsetAsync(zero, 0, (size_t)np * sizeof(double), s);
+    if (e != hipSuccess) return e;
+    const int nb = (n + 3) / 4;
+    const double *nul = nullptr;
+    // v_0 = P z / ||P z||, P = D or I - D, z the fixed pseudo-random vector
+    hipLaunchKernelGGL(k_lanczos_start, dim3(1), dim3(1024), 0, s, t, n);
+    hipLaunchKernelGGL(k_lanczos_matvec, dim3(nb), dim3(256), 0, s, D, ldd, n, t,
+                       unocc ? -1.0 : 1.0, 0.0, unocc ? (const double *)t : nul, 1.0, nul, nul, v);
+    hipLaunchKernelGGL(k_lanczos_update, dim3(1), dim3(1024), 0, s, v, zero, n, ab, ab + k);
+    for (int j = 0; j < k; ++j) {
+        double *vj = v + (size_t)(j % 3) * np;
+        double *vp = v + (size_t)((j + 2) % 3) * np;
+        double *vn = v + (size_t)((j + 1) % 3) * np;
+        // t = (H - sigma I) v_j ; w = P t - beta_{j-1} v_{j-1}
+        hipLaunchKernelGGL(k_lanczos_matvec, dim3(nb), dim3(256), 0, s, H, ldh, n, vj, 1.0, sigma,
+                           nul, 0.0, nul, nul, t);
+        hipLaunchKernelGGL(k_lanczos_matvec, dim3(nb), dim3(256), 0, s, D, ldd, n, t,
+                           unocc ? -1.0 : 1.0, 0.0, unocc ? (const double *)t : nul, 1.0, vp,
+                           j ? ab + k + j - 1 : nul, vn);
         hipLaunchKernelGGL(k_lanczos_update, dim3(1), dim3(1024), 0, s, vn, vj, n, ab + j,
                            ab + k + j);
     }

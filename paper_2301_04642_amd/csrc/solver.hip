@@ -87,7 +87,7 @@ Layout plan_layout(int64_t n, bool finite, int prec) {
     L.off_tiles128 = off;
     off += round_up(tiles128 * 4, 256);
     L.off_lanczos = off;
-    off += round_up((3 * L.np + 2 * kMaxLanczos) * sizeof(double), 256);
+    off += round_up((5 * L.np + 2 * kMaxLanczos) * sizeof(double), 256);
     L.off_state = off;
     off += round_up(sizeof(DevState), 256);
     L.bytes = off;
@@ -586,7 +586,7 @@ int Ctx::refine_bounds(const double *Hp, int64_t ldh, DevState *h) {
     int k = opt.lanczos_steps > 0 ? std::min(opt.lanczos_steps, kMaxLanczos) : 16;
     k = (int)std::min<int64_t>(k, n);
     if (k < 2) return FDM_OK;
-    double *ab = r->lanczos + 3 * r->lay.np;
+    double *ab = r->lanczos + 5 * r->lay.np;
     hipError_t e = launch_lanczos(Hp, ldh, (int)n, (int)r->lay.np, k, r->lanczos, ab, s);
     if (e != hipSuccess) return hip_fail(e, "lanczos launch");
     std::vector<double> hab(2 * k);
@@ -636,6 +636,77 @@ int Ctx::refine_bounds(const double *Hp, int64_t ldh, DevState *h) {
     return e == hipSuccess ? FDM_OK : hip_fail(e, "set_bounds launch");
 }
 
+// k Lanczos steps on the projection of Hp - sigma I onto the occupied
+// (unocc = 0) or unoccupied (unocc = 1) subspace of the density matrix D.
+// Returns the extreme Ritz value (largest for the occupied side, smallest
+// for the unoccupied one) and its residual bound |beta_k s_k|.
+int Ctx::projected_ritz(const double *Hp, int64_t ldh, const double *D, int64_t ldd, int unocc,
+                        double sigma, int k, double *theta, double *resid) {
+    double *ab = r->lanczos + 5 * r->lay.np;
+    hipError_t e = launch_lanczos_proj(Hp, ldh, D, ldd, (int)n, (int)r->lay.np, k, unocc, sigma,
+                                       r->lanczos, ab, s);
+    if (e != hipSuccess) return hip_fail(e, "projected lanczos launch");
+    std::vector<double> hab(2 * k);
+    e = hipMemcpyAsync(hab.data(), ab, 2 * k * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    const double *alpha = hab.data(), *beta = hab.data() + k;
+    double scale = 0.0;
+    for (int j = 0; j < k; ++j) scale = std::max(scale, fabs(alpha[j]) + fabs(beta[j]));
+    int m = k;
+    for (int j = 0; j < k - 1; ++j)
+        if (!(beta[j] > 1e-13 * scale)) {
+            m = j + 1;
+            break;
+        }
+    std::vector<double> T((size_t)m * m, 0.0), w, V;
+    for (int j = 0; j < m; ++j) {
+        T[(size_t)j * m + j] = alpha[j];
+        if (j + 1 < m) T[(size_t)j * m + j + 1] = T[(size_t)(j + 1) * m + j] = beta[j];
+    }
+    small_eigh(m, T, w, V);
+    int ie = 0;
+    for (int i = 1; i < m; ++i)
+        if (unocc ? w[i] < w[ie] : w[i] > w[ie]) ie = i;
+    const double bk = (m == k) ? beta[k - 1] : 0.0;
+    *theta = w[ie];
+    *resid = fabs(bk * V[(size_t)(m - 1) * m + ie]);
+    return FDM_OK;
+}
+
+// HOMO / LUMO bounds for a later accelerated solve (an SCF step after this
+// one): the HOMO is the largest eigenvalue of Hp on range(D), the LUMO the
+// smallest on range(I - D).  Lanczos on D (Hp - e_min) D and on
+// (I - D)(Hp - e_max)(I - D) (the shifts keep the extreme eigenvalue on the
+// wanted side of the projections' zero eigenvalues) gives Ritz values
+// theta with residual bounds r; homo_ub = e_min + theta_max + r and
+// lumo_lb = e_max + theta_min - r (40 steps: on the test workloads these bound
+// the true HOMO / LUMO and keep 70-100% of the gap; 16-24 steps left one
+// LUMO bound above the LUMO).  A Ritz value that has not converged can still
+// miss the true extreme by more than r: the accelerated solve that uses the
+// bounds guards against that (divergence guard, plain SP2 rerun).
+int Ctx::estimate_gap(const double *Hp, int64_t ldh, const double *D, int64_t ldd) {
+    stats.homo_ub = stats.lumo_lb = NAN;
+    const int k = (int)std::min<int64_t>(40, n);
+    if (k < 2) return FDM_OK;
+    double th_o = 0.0, r_o = 0.0, th_u = 0.0, r_u = 0.0;
+    int rc = projected_ritz(Hp, ldh, D, ldd, 0, stats.e_min, k, &th_o, &r_o);
+    if (rc) return rc;
+    rc = projected_ritz(Hp, ldh, D, ldd, 1, stats.e_max, k, &th_u, &r_u);
+    if (rc) return rc;
+    // (plus 1e-6 of the width: D is itself converged only to tol, which
+    // moves the Ritz values of its subspaces by about that much)
+    const double pad = 1e-6 * (stats.e_max - stats.e_min);
+    const double hu = stats.e_min + th_o + r_o + pad;
+    const double ll = stats.e_max + th_u - r_u - pad;
+    if (std::isfinite(hu) && std::isfinite(ll) && hu < ll) {
+        stats.homo_ub = hu;
+        stats.lumo_lb = ll;
+    }
+    return FDM_OK;
+}
+
 int Ctx::solve_zero_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, double *E_band) {
     const bool accel = std::isfinite(opt.homo) && std::isfinite(opt.lumo) && opt.lumo > opt.homo;
     int rc = solve_zero_t_once(Hp, ldh, D, ldd, E_band, accel);
@@ -659,6 +730,10 @@ int Ctx::solve_zero_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, dou
         if (keep_acc == -1) stats.accelerated = -1;
         stats.fallback_fp64 = 1;
     }
+    stats.homo_ub = stats.lumo_lb = NAN;
+    const int64_t k = (int64_t)llround(n_occ);
+    if (rc == FDM_OK && status == FDM_OK && opt.estimate_gap && k > 0 && k < n)
+        rc = estimate_gap(Hp, ldh, D, ldd);
     return rc;
 }
 
@@ -845,6 +920,7 @@ int fdm_options_default(fdm_options *opt) {
     opt->lanczos_steps = 16;
     opt->homo = NAN;
     opt->lumo = NAN;
+    opt->estimate_gap = 0;
     return FDM_OK;
 }
 
@@ -912,6 +988,7 @@ int fermi_dm_solve(const double *Hp, int64_t N, int64_t ldh, double n_occ, doubl
     c.tol = tol;
     c.kT = kT;
     memset(&c.stats, 0, sizeof(c.stats));
+    c.stats.homo_ub = c.stats.lumo_lb = NAN;
     const Layout L = plan_layout(N, kT > 0.0, opt.precision);
     int rc = r->bind(L, opt.workspace, opt.workspace_bytes, c.s);
     if (rc == FDM_OK && opt.validate) rc = c.validate_symmetric(Hp, ldh);

@@ -20,7 +20,7 @@ struct Layout {
     int64_t n = 0, np = 0, ld = 0;
     int n64 = 0, n32 = 0;
     size_t off64 = 0, off32 = 0, off_part = 0, off_tiles64 = 0, off_tiles128 = 0, off_state = 0;
-    size_t off_lanczos = 0;  // 3 vectors of np doubles + alpha/beta (2 x kMaxLanczos)
+    size_t off_lanczos = 0;  // 5 vectors of np doubles + alpha/beta (2 x kMaxLanczos)
     size_t off16 = 0;        // hi/lo 16-bit companions of the FP32 buffers
     size_t bytes = 0;
     int ntiles64 = 0, ntiles128 = 0;
@@ -106,6 +106,9 @@ struct Ctx {
     int read_state(DevState *out);
     int bounds(const double *Hp, int64_t ldh, DevState *h);
     int refine_bounds(const double *Hp, int64_t ldh, DevState *h);
+    int estimate_gap(const double *Hp, int64_t ldh, const double *D, int64_t ldd);
+    int projected_ritz(const double *Hp, int64_t ldh, const double *D, int64_t ldd, int unocc,
+                       double sigma, int k, double *theta, double *resid);
     int finish(const double *Hp, int64_t ldh, const void *dm, int dm_f32, double *D, int64_t ldd,
                double *E_band);
     int validate_symmetric(const double *Hp, int64_t ldh);

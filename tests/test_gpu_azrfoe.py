@@ -123,3 +123,37 @@ def test_config1_full_size(fdm):
         assert abs(np.trace(d) - wl.n_occ) <= 1e-8
         assert idem_rows <= 1e-8
         assert sum(st.products) < 0.8 * sum(stp.products)
+
+
+@pytest.mark.parametrize("cfg,n", [(0, 256), (1, 1000), (1, 4000), (3, 2000)])
+def test_estimated_bounds_feed_the_next_solve(fdm, cfg, n):
+    """estimate_gap = 1: the solve reports HOMO/LUMO bounds from Lanczos on
+    the occupied / unoccupied subspaces of D; they bound the true HOMO and
+    LUMO here, and a second (accelerated) solve with them is correct."""
+    wl = workloads.config_workload(cfg, n=n)
+    lam = np.sort(wl.lam)
+    k = int(round(wl.n_occ))
+    homo, lumo = lam[k - 1], lam[k]
+    H = dev(wl.hp)
+    say("estimate gap", cfg, n)
+    _, e0, st0 = fdm.solve(H, wl.n_occ, 0.0, wl.tol, "fp64", estimate_gap=1)
+    hu, ll = st0.homo_ub, st0.lumo_lb
+    print(f"[report] estimate cfg{cfg} n={n}: homo {homo:.5f} <= {hu:.5f}, lumo {lumo:.5f} >= "
+          f"{ll:.5f}: estimated gap {ll - hu:.5f} of {lumo - homo:.5f}", flush=True)
+    assert np.isfinite(hu) and np.isfinite(ll) and hu < ll
+    assert hu >= homo - 1e-12 and ll <= lumo + 1e-12
+    _, e_ref, _, _ = reference(wl)
+    for prec in ("fp64", "fp32"):
+        D, e, st = fdm.solve(H, wl.n_occ, 0.0, wl.tol, prec, homo=hu, lumo=ll)
+        assert st.status == 0 and st.accelerated == 1
+        assert abs(e - e_ref) <= (1e-9 if prec == "fp64" else 1e-6)
+        assert np.isnan(st.homo_ub)  # not asked for
+
+
+def test_estimate_gap_not_asked_or_finite_t(fdm):
+    wl = workloads.config_workload(0, n=128)
+    _, _, st = fdm.solve(dev(wl.hp), wl.n_occ, 0.0, 1e-10, "fp64")
+    assert np.isnan(st.homo_ub) and np.isnan(st.lumo_lb)
+    wl = workloads.config_workload(2, n=128)
+    _, _, st = fdm.solve(dev(wl.hp), wl.n_occ, wl.kT, 1e-9, "fp64", estimate_gap=1)
+    assert np.isnan(st.homo_ub) and np.isnan(st.lumo_lb)

@@ -19,7 +19,7 @@ enum Prec : int { P_F64 = 0, P_F32 = 1, P_F16X3 = 2, P_BF16X3 = 3, P_BF16 = 4, P
 // checks.
 constexpr int kPadEdge = 128;
 // K is swept in stages of this many elements (all precisions divide it).
-constexpr int kKStep = 32;
+constexpr int kKStep = 64;  // K extent granule: two stages of every precision
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 

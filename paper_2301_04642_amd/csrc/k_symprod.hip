@@ -354,24 +354,26 @@ void k_symprod(ProdArgs a) {
     };
 
     // Stage kt lives in LDS buffer kt & 1; the loop is unrolled by two so
-    // buffer and register-set indices are static.  FP32 prefetches two
-    // stages ahead (register set kt & 1 carries stage kt; 1% faster at
-    // N = 4000 and 16000); FP64 has no registers left for the second set,
-    // and the split forms spend them on the running fold accumulator (two
-    // sets and the fold spill: 570 -> 340 TFLOP/s), so both prefetch one
-    // stage ahead.
-    if constexpr (P == P_F32) {
+    // buffer and register-set indices are static.  FP64 and FP32 prefetch
+    // two stages ahead (register set kt & 1 carries stage kt); the split
+    // forms spend those registers on the running fold accumulator (two sets
+    // and the fold spill: 570 -> 340 TFLOP/s) and prefetch one stage ahead.
+    // kext is a multiple of 64, so nk is even and every trip runs both
+    // halves.  The loads are unconditional (stages past the end reload the
+    // last one, in bounds and unused): a conditional load makes the
+    // compiler's in-order vmcnt accounting wait for the newer set too, which
+    // serialises the loads with the MFMAs.
+    if constexpr (P == P_F32 || P == P_F64) {
         gload(0, ga0, gb0);
-        if (nk > 1) gload(1, ga1, gb1);
+        gload(1, ga1, gb1);
         lstore(0, ga0, gb0);
         __syncthreads();
         for (int kt = 0; kt < nk; kt += 2) {
-            if (kt + 2 < nk) gload(kt + 2, ga0, gb0);
+            gload(kt + 2 < nk ? kt + 2 : nk - 1, ga0, gb0);
             compute(0, kt);
-            if (kt + 1 < nk) lstore(1, ga1, gb1);
+            lstore(1, ga1, gb1);
             __syncthreads();
-            if (kt + 1 >= nk) break;
-            if (kt + 3 < nk) gload(kt + 3, ga1, gb1);
+            gload(kt + 3 < nk ? kt + 3 : nk - 1, ga1, gb1);
             compute(1, kt + 1);
             if (kt + 2 < nk) lstore(0, ga0, gb0);
             __syncthreads();
@@ -381,12 +383,11 @@ void k_symprod(ProdArgs a) {
         lstore(0, ga0, gb0);
         __syncthreads();
         for (int kt = 0; kt < nk; kt += 2) {
-            if (kt + 1 < nk) gload(kt + 1, ga0, gb0);
+            gload(kt + 1, ga0, gb0);
             compute(0, kt);
-            if (kt + 1 < nk) lstore(1, ga0, gb0);
+            lstore(1, ga0, gb0);
             __syncthreads();
-            if (kt + 1 >= nk) break;
-            if (kt + 2 < nk) gload(kt + 2, ga0, gb0);
+            gload(kt + 2 < nk ? kt + 2 : nk - 1, ga0, gb0);
             compute(1, kt + 1);
             if (kt + 2 < nk) lstore(0, ga0, gb0);
             __syncthreads();

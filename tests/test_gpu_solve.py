@@ -229,3 +229,33 @@ def test_low_precision_cap_falls_back_to_fp64(fdm):
     assert st.fallback_fp64 == 1
     assert st.iters_fp64 == 8 and st.status == fdm.FDM_ENOCONV
     assert st.products[fdm.FDM_FP32] >= 8 and st.products[fdm.FDM_FP64] >= 8
+
+
+@pytest.mark.parametrize("prec,kT", [("fp64", 0.0), ("fp16x3", 0.0), ("fp32", 0.0016)])
+def test_caller_workspace(fdm, prec, kT):
+    """A caller-owned workspace of fdm_workspace_bytes() gives bitwise the
+    result of the library's own; a smaller one is refused (EINVAL)."""
+    import torch
+    wl = workloads.config_workload(2 if kT else 1, n=300)
+    H = dev(wl.hp)
+    tol = 1e-9 if kT else wl.tol
+    D0, e0, st0 = fdm.solve(H, wl.n_occ, kT, tol, prec, estimate_gap=0 if kT else 1)
+    nb = fdm.fdm_workspace_bytes(wl.n, kT, fdm.PRECISIONS[prec])
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    D1, e1, st1 = fdm.solve(H, wl.n_occ, kT, tol, prec, estimate_gap=0 if kT else 1,
+                            workspace=ws.data_ptr(), workspace_bytes=nb)
+    assert st1.status == 0 and e1 == e0
+    assert torch.equal(D0, D1)
+    if not kT:
+        assert st1.homo_ub == st0.homo_ub and st1.lumo_lb == st0.lumo_lb
+    rc, _, _ = fdm.fermi_dm_solve(H, wl.n_occ, kT, tol, torch.empty_like(H),
+                                  _opts(fdm, prec, ws, nb - 256), raise_on_error=False)
+    assert rc == fdm.FDM_EINVAL
+
+
+def _opts(fdm, prec, ws, nbytes):
+    o = fdm.fdm_options_default()
+    o.precision = fdm.PRECISIONS[prec]
+    o.workspace = ws.data_ptr()
+    o.workspace_bytes = nbytes
+    return o

@@ -272,7 +272,7 @@ def main():
         log(f"calibration copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written")
         del src, dst
     log("generating workload")
-    wl = workloads.config_workload(1, n=args.n)
+    wl = workloads.standard_workload("bands", n=args.n)
     e_ref = float(np.sort(wl.lam)[: int(wl.n_occ)].sum())   # sum of the n_occ lowest
     H = torch.from_numpy(wl.hp).cuda()
     suffix = "+lanczos" if args.bounds == "lanczos" else ""

@@ -65,7 +65,7 @@ def check_jacobi_vs_lapack(eigh=jacobi_eigh, n=64):
 
 
 def check_density_invariants(density_matrix=den.density_matrix, n=64):
-    wl = workloads.config_workload(0, n=n)
+    wl = workloads.standard_workload("gapped", n=n)
     d, e, mu, lam = density_matrix(wl.hp, wl.n_occ, 0.0)
     assert np.linalg.norm(d @ d - d) < 1e-11
     assert abs(np.trace(d) - wl.n_occ) < 1e-11
@@ -76,8 +76,7 @@ def check_density_invariants(density_matrix=den.density_matrix, n=64):
 
 
 def check_density_vs_construction(density_matrix=den.density_matrix, n=80, kT=0.0):
-    c = 0 if kT == 0.0 else 2
-    wl = workloads.config_workload(c, n=n)
+    wl = workloads.standard_workload("gapped" if kT == 0.0 else "uniform", n=n)
     d, e, mu, lam = density_matrix(wl.hp, wl.n_occ, kT)
     f, mu2 = den.occupations(wl.lam, wl.n_occ, kT)
     d_ref = (wl.q * f) @ wl.q.T
@@ -87,7 +86,7 @@ def check_density_vs_construction(density_matrix=den.density_matrix, n=80, kT=0.
 
 
 def check_shift_scale_and_permutation(density_matrix=den.density_matrix, n=40):
-    wl = workloads.config_workload(0, n=n)
+    wl = workloads.standard_workload("gapped", n=n)
     d, *_ = density_matrix(wl.hp, wl.n_occ, 0.0)
     d2, *_ = density_matrix(2.5 * wl.hp - 0.7 * np.eye(n), wl.n_occ, 0.0)
     assert np.abs(d - d2).max() < 1e-12
@@ -124,7 +123,7 @@ def check_fd_symmetric_mu(chem=den.chemical_potential):
 
 
 def check_fd_low_t_limit(n=64):
-    wl = workloads.config_workload(0, n=n)
+    wl = workloads.standard_workload("gapped", n=n)
     d0, e0, *_ = den.density_matrix(wl.hp, wl.n_occ, 0.0)
     d1, e1, *_ = den.density_matrix(wl.hp, wl.n_occ, 1e-4)   # gap 0.2 Ha >> kT
     assert np.abs(d0 - d1).max() < 1e-12
@@ -138,7 +137,7 @@ def check_gershgorin(bounds=sp2.gershgorin_bounds):
     assert np.allclose(bounds(np.array([[a, b], [b, c]])), (a - abs(b), c + abs(b)))
     h = np.array([[1.0, 0.5, -0.25], [0.5, -2.0, 1.0], [-0.25, 1.0, 0.0]])
     assert np.allclose(bounds(h), (-3.5, 1.75))
-    wl = workloads.config_workload(1, n=200)
+    wl = workloads.standard_workload("bands", n=200)
     lo, hi = bounds(wl.hp)
     assert lo <= wl.lam.min() and hi >= wl.lam.max()
 
@@ -162,7 +161,7 @@ def check_sp2_diagonal(sp2fn=sp2.sp2):
 
 def check_sp2_matches_definition(sp2fn=sp2.sp2, sizes=(4, 16, 64, 256)):
     for n in sizes:
-        wl = workloads.config_workload(0, n=n)
+        wl = workloads.standard_workload("gapped", n=n)
         x, info = sp2fn(wl.hp, wl.n_occ, tol=1e-11)
         f, _ = den.occupations(wl.lam, wl.n_occ, 0.0)
         d_ref, e_ref = den.density_from_eig(wl.q, wl.lam, f)
@@ -197,7 +196,7 @@ def check_fd_recursion_closed_form(doubling=fd.doubling):
 
 
 def check_fd_recursion_dense(doubling=fd.doubling, n=64):
-    wl = workloads.config_workload(2, n=n)
+    wl = workloads.standard_workload("uniform", n=n)
     kT = 0.0016
     f, mu = den.occupations(wl.lam, wl.n_occ, kT)
     d_ref, _ = den.density_from_eig(wl.q, wl.lam, f)
@@ -270,7 +269,7 @@ def check_azrfoe_matches_definition(azfn=az.azrfoe, sizes=(16, 64, 256), shrink=
     """Dense H: the accelerated expansion reaches the definition theta(mu - H)
     with exact HOMO/LUMO bounds and with bounds that understate the gap."""
     for n in sizes:
-        wl = workloads.config_workload(0, n=n)
+        wl = workloads.standard_workload("gapped", n=n)
         k = int(wl.n_occ)
         lam = np.sort(wl.lam)
         gap = lam[k] - lam[k - 1]

@@ -37,7 +37,7 @@ def gap_bounds(wl, shrink=0.0):
 def test_fp64_matches_oracle(fdm, n, shrink):
     from oracle import azrfoe as az
     from oracle import density as den
-    wl = workloads.config_workload(0, n=n)
+    wl = workloads.standard_workload("gapped", n=n)
     homo, lumo = gap_bounds(wl, shrink)
     d_ref, e_ref, _, _ = reference(wl)
     say("azrfoe fp64", n, shrink)
@@ -63,7 +63,7 @@ def test_fp64_matches_oracle(fdm, n, shrink):
 
 @pytest.mark.parametrize("prec", MIXED)
 def test_mixed_bands(fdm, prec):
-    wl = workloads.config_workload(1, n=1000)
+    wl = workloads.standard_workload("bands", n=1000)
     d_ref, e_ref, _, _ = reference(wl)
     homo, lumo = gap_bounds(wl, 0.25)
     say("azrfoe", prec, wl.n)
@@ -87,7 +87,7 @@ def test_wrong_bounds_fall_back(fdm, prec):
     """HOMO bound 0.3 Ha below the HOMO and LUMO bound 0.3 Ha above the LUMO:
     the accelerated polynomials throw states out of [0, 1]; the device ends
     that phase and the solve repeats as plain SP2."""
-    wl = workloads.config_workload(0, n=256)
+    wl = workloads.standard_workload("gapped", n=256)
     d_ref, e_ref, _, _ = reference(wl)
     homo, lumo = gap_bounds(wl)
     say("azrfoe wrong bounds", prec)
@@ -99,23 +99,23 @@ def test_wrong_bounds_fall_back(fdm, prec):
     assert abs(np.trace(d) - wl.n_occ) <= 1e-8
 
 
-def test_config1_full_size(fdm):
+def test_bands_n4000_full_size(fdm):
     """N = 4000 band workload, FP64 and FP32 with bounds that understate the
     gap by 25%: same gates as the plain forms, about half the products."""
-    wl = workloads.config_workload(1)
+    wl = workloads.standard_workload("bands")
     homo, lumo = gap_bounds(wl, 0.25)
     from oracle import density as den
     f, _ = den.occupations(wl.lam, wl.n_occ, 0.0)
     e_ref = float(np.dot(f, wl.lam))
     H = dev(wl.hp)
     for prec in ("fp64", "fp32"):
-        say("azrfoe config1", prec)
+        say("azrfoe bands N=4000", prec)
         D, e, st = fdm.solve(H, wl.n_occ, 0.0, wl.tol, prec, homo=homo, lumo=lumo)
         _, _, stp = fdm.solve(H, wl.n_occ, 0.0, wl.tol, prec)
         d = host(D)
         rows = np.random.default_rng(3).choice(wl.n, 4, replace=False)
         idem_rows = np.linalg.norm(d[rows] @ d - d[rows])
-        print(f"[report] azrfoe config1 {prec}: products {sum(st.products)} "
+        print(f"[report] azrfoe bands-n4000 {prec}: products {sum(st.products)} "
               f"(plain {sum(stp.products)}) |dE|={abs(e - e_ref):.2e} "
               f"|dTr|={abs(np.trace(d) - wl.n_occ):.2e} rows idem={idem_rows:.1e}", flush=True)
         assert st.status == 0 and st.accelerated == 1
@@ -125,20 +125,20 @@ def test_config1_full_size(fdm):
         assert sum(st.products) < 0.8 * sum(stp.products)
 
 
-@pytest.mark.parametrize("cfg,n", [(0, 256), (1, 1000), (1, 4000), (3, 2000)])
-def test_estimated_bounds_feed_the_next_solve(fdm, cfg, n):
+@pytest.mark.parametrize("kind,n", [("gapped", 256), ("bands", 1000), ("bands", 4000), ("outliers", 2000)])
+def test_estimated_bounds_feed_the_next_solve(fdm, kind, n):
     """estimate_gap = 1: the solve reports HOMO/LUMO bounds from Lanczos on
     the occupied / unoccupied subspaces of D; they bound the true HOMO and
     LUMO here, and a second (accelerated) solve with them is correct."""
-    wl = workloads.config_workload(cfg, n=n)
+    wl = workloads.standard_workload(kind, n=n)
     lam = np.sort(wl.lam)
     k = int(round(wl.n_occ))
     homo, lumo = lam[k - 1], lam[k]
     H = dev(wl.hp)
-    say("estimate gap", cfg, n)
+    say("estimate gap", kind, n)
     _, e0, st0 = fdm.solve(H, wl.n_occ, 0.0, wl.tol, "fp64", estimate_gap=1)
     hu, ll = st0.homo_ub, st0.lumo_lb
-    print(f"[report] estimate cfg{cfg} n={n}: homo {homo:.5f} <= {hu:.5f}, lumo {lumo:.5f} >= "
+    print(f"[report] estimate {kind} n={n}: homo {homo:.5f} <= {hu:.5f}, lumo {lumo:.5f} >= "
           f"{ll:.5f}: estimated gap {ll - hu:.5f} of {lumo - homo:.5f}", flush=True)
     assert np.isfinite(hu) and np.isfinite(ll) and hu < ll
     assert hu >= homo - 1e-12 and ll <= lumo + 1e-12
@@ -151,9 +151,9 @@ def test_estimated_bounds_feed_the_next_solve(fdm, cfg, n):
 
 
 def test_estimate_gap_not_asked_or_finite_t(fdm):
-    wl = workloads.config_workload(0, n=128)
+    wl = workloads.standard_workload("gapped", n=128)
     _, _, st = fdm.solve(dev(wl.hp), wl.n_occ, 0.0, 1e-10, "fp64")
     assert np.isnan(st.homo_ub) and np.isnan(st.lumo_lb)
-    wl = workloads.config_workload(2, n=128)
+    wl = workloads.standard_workload("uniform", n=128)
     _, _, st = fdm.solve(dev(wl.hp), wl.n_occ, wl.kT, 1e-9, "fp64", estimate_gap=1)
     assert np.isnan(st.homo_ub) and np.isnan(st.lumo_lb)

@@ -41,7 +41,7 @@ def test_operator_closed_form_diagonal(fdm):
 def test_operator_dense_matches_oracle_recursion(fdm, n):
     import torch
     from oracle import fd
-    wl = workloads.config_workload(2, n=n)
+    wl = workloads.standard_workload("uniform", n=n)
     mu = -0.41
     H = dev(wl.hp)
     D = torch.empty_like(H)
@@ -60,7 +60,7 @@ def test_operator_dense_matches_oracle_recursion(fdm, n):
 def test_operator_low_precision(fdm, prec):
     import torch
     from oracle import fd
-    wl = workloads.config_workload(2, n=200)
+    wl = workloads.standard_workload("uniform", n=200)
     mu = -0.5
     H = dev(wl.hp)
     D = torch.empty_like(H)
@@ -102,11 +102,11 @@ def check_solve(fdm, wl, prec):
 
 @pytest.mark.parametrize("n", [100, 257, 600])
 def test_solve_fp64(fdm, n):
-    check_solve(fdm, workloads.config_workload(2, n=n), "fp64")
+    check_solve(fdm, workloads.standard_workload("uniform", n=n), "fp64")
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp16x3", "bf16x3"])
 def test_solve_mixed_final_fp64(fdm, prec):
     """Low-precision mu search, one FP64 evaluation and the trace correction."""
-    st = check_solve(fdm, workloads.config_workload(2, n=400), prec)
+    st = check_solve(fdm, workloads.standard_workload("uniform", n=400), prec)
     assert st.products[fdm.PRECISIONS[prec]] > 0 and st.products[0] > 0

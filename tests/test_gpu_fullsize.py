@@ -35,26 +35,26 @@ def sampled_checks(wl, d, f, rows, tol_rows, tol_idem, tol_comm=None):
 
 
 @pytest.fixture(scope="module")
-def config3():
-    say("generate config3 N=30000")
-    return workloads.config_workload(3)
+def outliers30000():
+    say("generate bands+outliers N=30000")
+    return workloads.standard_workload("outliers")
 
 
 @pytest.mark.parametrize("prec,bounds", [("fp32", 0), ("fp32", 1), ("fp16x3", 1)])
-def test_config3_n30000_mixed(fdm, config3, prec, bounds):
+def test_outliers_n30000_mixed(fdm, outliers30000, prec, bounds):
     """N = 30000, n_occ = 7500, bands + 1% outliers up to 5 Ha, gap 0.05 Ha:
     FP32 bulk with FP64 first steps, traces and McWeeny refinement."""
     from oracle import density as den
-    wl = config3
+    wl = outliers30000
     H = dev(wl.hp)
-    say("solve config3", prec, "bounds", bounds)
+    say("solve bands+outliers N=30000", prec, "bounds", bounds)
     D, e, st = fdm.solve(H, wl.n_occ, 0.0, 1e-8, prec, bounds=bounds)
     del H
     d = host(D)
     del D
     f, _ = den.occupations(wl.lam, wl.n_occ, 0.0)
     e_ref = float(np.dot(f, wl.lam))
-    print(f"[report] config3 {prec} bounds={bounds}: k64={st.iters_fp64_first} low={st.iters_low} mcw={st.mcweeny_steps} "
+    print(f"[report] outliers-n30000 {prec} bounds={bounds}: k64={st.iters_fp64_first} low={st.iters_low} mcw={st.mcweeny_steps} "
           f"|dE|={abs(e - e_ref):.2e} idem={st.idempotency:.2e} bounds=({st.e_min:.1f},{st.e_max:.1f})",
           flush=True)
     assert st.status == 0
@@ -66,19 +66,19 @@ def test_config3_n30000_mixed(fdm, config3, prec, bounds):
     sampled_checks(wl, d, f, rows, tol_rows=1e-4, tol_idem=1e-8)
 
 
-def test_config2_n12000_finite_t_mixed(fdm):
+def test_uniform_n12000_finite_t_mixed(fdm):
     """N = 12000, uniform [-1, 1], kT = 0.0016 Ha, n_occ = 3000: FP16x3 mu
     search, one FP64 evaluation and the first-order trace correction."""
     from oracle import density as den
-    say("generate config2 N=12000")
-    wl = workloads.config_workload(2)
+    say("generate uniform N=12000")
+    wl = workloads.standard_workload("uniform")
     H = dev(wl.hp)
-    say("solve config2 fp16x3")
+    say("solve uniform N=12000 fp16x3")
     D, e, st = fdm.solve(H, wl.n_occ, wl.kT, 1e-6, "fp16x3")
     d = host(D)
     f, mu = den.occupations(wl.lam, wl.n_occ, wl.kT)
     e_ref = float(np.dot(f, wl.lam))
-    print(f"[report] config2: evals={st.mu_evals} depth={st.depth} mu={st.mu:.9f} (exact {mu:.9f}) "
+    print(f"[report] uniform-n12000: evals={st.mu_evals} depth={st.depth} mu={st.mu:.9f} (exact {mu:.9f}) "
           f"|dE|={abs(e - e_ref):.2e} |dTr|={abs(np.trace(d) - wl.n_occ):.2e}", flush=True)
     assert st.status == 0
     assert abs(e - e_ref) <= 1e-6
@@ -89,6 +89,6 @@ def test_config2_n12000_finite_t_mixed(fdm):
     err = np.abs(d[rows] - ref_rows).max()
     hr = wl.hp[rows]
     comm = np.linalg.norm(hr @ d - d[rows] @ wl.hp)
-    print(f"[report] config2: sampled-row max err {err:.2e}, row commutator {comm:.2e}", flush=True)
+    print(f"[report] uniform-n12000: sampled-row max err {err:.2e}, row commutator {comm:.2e}", flush=True)
     assert err <= 1e-5
     assert comm <= 1e-6

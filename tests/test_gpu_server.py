@@ -66,11 +66,11 @@ def test_budget_enforced(fdm):
     foot = fdm.fdm_workspace_bytes(n, 0.0, fdm.FDM_FP32) + 2 * n * n * 8
     srv = fdm.Server(budget_bytes=foot + foot // 2, max_active=4, precision="fp32")
     try:
-        big = workloads.config_workload(0, n=600)
+        big = workloads.standard_workload("gapped", n=600)
         with pytest.raises(fdm.FdmError) as ei:
             srv.submit(big.hp, big.n_occ, 0.0, 1e-8)
         assert ei.value.code == fdm.FDM_ENOMEM
-        wls = [workloads.config_workload(0, n=n, seed_base=77 + i) for i in range(4)]
+        wls = [workloads.standard_workload("gapped", n=n, seed_base=77 + i) for i in range(4)]
         say("budget: serial admission")
         ts = [srv.submit(w.hp, w.n_occ, 0.0, 1e-8) for w in wls]
         spans = []
@@ -87,7 +87,7 @@ def test_budget_enforced(fdm):
 
 
 def test_device_input_and_poll(fdm):
-    wl = workloads.config_workload(0, n=200)
+    wl = workloads.standard_workload("gapped", n=200)
     srv = fdm.Server(budget_bytes=1 << 30, max_active=2, precision="fp64")
     try:
         say("device input")

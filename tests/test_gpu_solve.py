@@ -45,22 +45,22 @@ def check_fp64(fdm, wl, tol=1e-11, **opts):
 
 
 @pytest.mark.parametrize("bounds", [0, 1])
-def test_config0_fp64(fdm, bounds):
+def test_gapped_n256_fp64(fdm, bounds):
     """N = 256, n_occ = 64, gap 0.2 Ha (the small FP64 configuration)."""
-    st = check_fp64(fdm, workloads.config_workload(0), tol=1e-10, bounds=bounds)
+    st = check_fp64(fdm, workloads.standard_workload("gapped"), tol=1e-10, bounds=bounds)
     assert 15 <= st.iters_fp64 <= 60
 
 
 @pytest.mark.parametrize("n", [2, 7, 63, 64, 65, 127, 129, 300])
 def test_ragged_sizes_fp64(fdm, n):
-    check_fp64(fdm, workloads.config_workload(0, n=n))
+    check_fp64(fdm, workloads.standard_workload("gapped", n=n))
 
 
-@pytest.mark.parametrize("cfg,n", [(0, 256), (1, 1000), (3, 1200), (0, 9)])
-def test_lanczos_bounds(fdm, cfg, n):
+@pytest.mark.parametrize("kind,n", [("gapped", 256), ("bands", 1000), ("outliers", 1200), ("gapped", 9)])
+def test_lanczos_bounds(fdm, kind, n):
     """Tightened bounds bracket the exact spectrum, stay inside Gershgorin,
     are within 5% of the spectral width, and cut the SP2 product count."""
-    wl = workloads.config_workload(cfg, n=n)
+    wl = workloads.standard_workload(kind, n=n)
     lam = np.sort(wl.lam)
     st_g = check_fp64(fdm, wl, bounds=0)
     st = check_fp64(fdm, wl, bounds=1)
@@ -76,13 +76,13 @@ def test_lanczos_bounds(fdm, cfg, n):
 
 @pytest.mark.parametrize("tile", [64, 128])
 def test_tiles_agree(fdm, tile):
-    wl = workloads.config_workload(1, n=500)
+    wl = workloads.standard_workload("bands", n=500)
     check_fp64(fdm, wl, tol=1e-10, tile=tile)
 
 
 def test_special_cases(fdm):
     import torch
-    wl = workloads.config_workload(0, n=40)
+    wl = workloads.standard_workload("gapped", n=40)
     H = dev(wl.hp)
     say("special n_occ=0")
     D, e, st = fdm.solve(H, 0, 0.0, 1e-10)
@@ -99,7 +99,7 @@ def test_special_cases(fdm):
 
 def test_error_paths(fdm):
     import torch
-    wl = workloads.config_workload(0, n=64)
+    wl = workloads.standard_workload("gapped", n=64)
     H = dev(wl.hp)
     D = torch.empty_like(H)
     say("errors")
@@ -134,7 +134,7 @@ def test_error_paths(fdm):
 
 def test_leading_dimensions(fdm):
     import torch
-    wl = workloads.config_workload(0, n=100)
+    wl = workloads.standard_workload("gapped", n=100)
     Hb = torch.full((100, 132), 7.0, dtype=torch.float64, device="cuda")
     Hb[:, :100] = dev(wl.hp)
     Db = torch.full((100, 120), -3.0, dtype=torch.float64, device="cuda")
@@ -172,58 +172,58 @@ def check_mixed(fdm, wl, prec, gate=True, **opts):
 
 @pytest.mark.parametrize("prec", MIXED)
 def test_mixed_bands_small(fdm, prec):
-    check_mixed(fdm, workloads.config_workload(1, n=1000), prec, bounds=0)
+    check_mixed(fdm, workloads.standard_workload("bands", n=1000), prec, bounds=0)
 
 
 @pytest.mark.parametrize("prec", MIXED)
 def test_mixed_bands_lanczos(fdm, prec):
-    check_mixed(fdm, workloads.config_workload(1, n=1000), prec, bounds=1)
+    check_mixed(fdm, workloads.standard_workload("bands", n=1000), prec, bounds=1)
 
 
 @pytest.mark.parametrize("prec", MIXED)
 def test_mixed_k64_zero(fdm, prec):
     """Low precision from the first step (no FP64-first phase)."""
-    st, _ = check_mixed(fdm, workloads.config_workload(0, n=500), prec, k64=0)
+    st, _ = check_mixed(fdm, workloads.standard_workload("gapped", n=500), prec, k64=0)
     assert st.iters_fp64_first == 0 and st.iters_low > 0
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
 def test_plain_half_forms_reported(fdm, prec):
-    st, de = check_mixed(fdm, workloads.config_workload(1, n=1000), prec, gate=False)
+    st, de = check_mixed(fdm, workloads.standard_workload("bands", n=1000), prec, gate=False)
     assert np.isfinite(de)
 
 
 @pytest.fixture(scope="module")
-def config1():
-    return workloads.config_workload(1)
+def bands4000():
+    return workloads.standard_workload("bands")
 
 
 @pytest.mark.parametrize("prec", ["fp64"] + MIXED)
-def test_config1_full_size(fdm, config1, prec):
+def test_bands_n4000_full_size(fdm, bands4000, prec):
     """N = 4000, 20 bands, gap 0.02 Ha, tol 1e-8: the benchmark workload."""
     if prec == "fp64":
-        d_ref, e_ref, _, _ = reference(config1)
-        say("config1 fp64 tol 1e-8")
-        D, e, st = fdm.solve(dev(config1.hp), config1.n_occ, 0.0, 1e-8, "fp64")
+        d_ref, e_ref, _, _ = reference(bands4000)
+        say("bands N=4000 fp64 tol 1e-8")
+        D, e, st = fdm.solve(dev(bands4000.hp), bands4000.n_occ, 0.0, 1e-8, "fp64")
         assert st.idempotency <= 1e-8
         assert abs(e - e_ref) <= 1e-8          # first order in the idempotency error
-        say("config1 fp64 tol 1e-11")
-        D, e, st = fdm.solve(dev(config1.hp), config1.n_occ, 0.0, 1e-11, "fp64")
+        say("bands N=4000 fp64 tol 1e-11")
+        D, e, st = fdm.solve(dev(bands4000.hp), bands4000.n_occ, 0.0, 1e-11, "fp64")
         d = host(D)
         assert abs(e - e_ref) <= 1e-10
         assert np.linalg.norm(d - d_ref) <= 1e-10
-        assert abs(np.trace(d) - config1.n_occ) <= 1e-10
+        assert abs(np.trace(d) - bands4000.n_occ) <= 1e-10
         assert st.idempotency <= 1e-11
     else:
-        check_mixed(fdm, config1, prec, bounds=0)
-        check_mixed(fdm, config1, prec, bounds=1)
+        check_mixed(fdm, bands4000, prec, bounds=0)
+        check_mixed(fdm, bands4000, prec, bounds=1)
 
 
 def test_low_precision_cap_falls_back_to_fp64(fdm):
     """A low-precision phase that runs out of steps above tau hands the solve
     to FP64 from the start (here the step cap is too small for either, so the
     FP64 pass reports ENOCONV after the fallback)."""
-    wl = workloads.config_workload(0)
+    wl = workloads.standard_workload("gapped")
     D, e, st = fdm.solve(dev(wl.hp), wl.n_occ, 0.0, 1e-10, "fp32", raise_on_error=False,
                          max_iter=8, k64=0)
     assert st.fallback_fp64 == 1
@@ -236,7 +236,7 @@ def test_caller_workspace(fdm, prec, kT):
     """A caller-owned workspace of fdm_workspace_bytes() gives bitwise the
     result of the library's own; a smaller one is refused (EINVAL)."""
     import torch
-    wl = workloads.config_workload(2 if kT else 1, n=300)
+    wl = workloads.standard_workload("uniform" if kT else 1, n=300)
     H = dev(wl.hp)
     tol = 1e-9 if kT else wl.tol
     D0, e0, st0 = fdm.solve(H, wl.n_occ, kT, tol, prec, estimate_gap=0 if kT else 1)

@@ -21,7 +21,7 @@ def test_sp2_iteration_count_plausible():
     """Sec. IV reports about 50 SP2 products at its tolerance; a dense rotated
     band spectrum with Gershgorin bounds needs a similar count here."""
     import workloads
-    wl = workloads.config_workload(1, n=400)
+    wl = workloads.standard_workload("bands", n=400)
     x, info = sp2.sp2(wl.hp, wl.n_occ, tol=1e-8)
     assert info["converged"]
     assert 35 <= info["iterations"] <= 65, info["iterations"]

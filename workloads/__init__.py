@@ -13,11 +13,11 @@ from .gen import (  # noqa: F401
     spectrum_bands_outliers,
     spectrum_uniform,
     make_workload,
-    config_workload,
+    standard_workload,
     serving_requests,
     paper_e1_band,
     paper_e1_matrix,
     paper_e1_rows,
     serving_workload,
-    CONFIGS,
+    WORKLOADS,
 )

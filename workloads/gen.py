@@ -167,35 +167,42 @@ def make_workload(name: str, lam: np.ndarray, n_occ: float, kT: float, tol: floa
 
 KT_500K = 0.0016  # Ha; 500 K is 1.583e-3 Ha, rounded as in the benchmark definition
 
-CONFIGS = {
-    0: dict(name="gapped-n256-fp64", n=256, n_occ=64, kT=0.0, tol=1e-10),
-    1: dict(name="bands-n4000-gap0.02", n=4000, n_occ=1000, kT=0.0, tol=1e-8),
-    2: dict(name="uniform-n12000-kT0.0016", n=12000, n_occ=3000, kT=KT_500K, tol=1e-8),
-    3: dict(name="bands-outliers-n30000-gap0.05", n=30000, n_occ=7500, kT=0.0, tol=1e-8),
+# The standard workloads: the recipes of the gapped small case, the 20-band
+# case, the gapless uniform finite-temperature case and the band case with
+# outliers, at their full sizes (smaller n keeps the recipe).
+WORKLOADS = {
+    "gapped": dict(name="gapped-n256", n=256, n_occ=64, kT=0.0, tol=1e-10, seed=1000),
+    "bands": dict(name="bands-n4000-gap0.02", n=4000, n_occ=1000, kT=0.0, tol=1e-8, seed=2000),
+    "uniform": dict(name="uniform-n12000-kT0.0016", n=12000, n_occ=3000, kT=KT_500K, tol=1e-8,
+                    seed=3000),
+    "outliers": dict(name="bands-outliers-n30000-gap0.05", n=30000, n_occ=7500, kT=0.0, tol=1e-8,
+                     seed=4000),
 }
 
 
-def config_workload(c: int, n: Optional[int] = None, seed_base: Optional[int] = None) -> Workload:
-    """Workload of benchmark configuration c (0..3), optionally at a smaller n
-    with the same recipe (n_occ scales as n/4; config 0 keeps its fractions)."""
-    cfg = CONFIGS[c]
+def standard_workload(kind: str, n: Optional[int] = None,
+                      seed_base: Optional[int] = None) -> Workload:
+    """One of the standard workloads ("gapped": 64 of 256 states in
+    [-1, -0.2] and the rest in [0, 1.5], gap 0.2 Ha; "bands": 20 Gaussian
+    bands, gap 0.02 Ha at N/4; "uniform": uniform [-1, 1] at kT = 0.0016 Ha;
+    "outliers": bands plus 1% outliers in [1.5, 5], gap 0.05 Ha), optionally
+    at a smaller n with the same recipe (n_occ = n/4)."""
+    cfg = WORKLOADS[kind]
     n = cfg["n"] if n is None else int(n)
-    seed = 1000 * (c + 1) if seed_base is None else seed_base
+    seed = cfg["seed"] if seed_base is None else seed_base
     rng = np.random.default_rng(seed + 2)
-    if c == 0:
+    if kind == "gapped":
         n_occ = max(1, n // 4) if n > 1 else 0
         lam = spectrum_gapped_uniform(n, n_occ, (-1.0, -0.2), (0.0, 1.5), rng)
-    elif c == 1:
+    elif kind == "bands":
         n_occ = n // 4
         lam = spectrum_bands(n, n_occ, 0.02, rng)
-    elif c == 2:
+    elif kind == "uniform":
         n_occ = n // 4
         lam = spectrum_uniform(n, -1.0, 1.0, rng)
-    elif c == 3:
+    else:
         n_occ = n // 4
         lam = spectrum_bands_outliers(n, n_occ, 0.05, rng)
-    else:
-        raise ValueError(c)
     name = cfg["name"] if n == cfg["n"] else f"{cfg['name']}@n{n}"
     return make_workload(name, lam, float(n_occ), cfg["kT"], cfg["tol"], seed + 1)
 

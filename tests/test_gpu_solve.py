@@ -236,7 +236,7 @@ def test_caller_workspace(fdm, prec, kT):
     """A caller-owned workspace of fdm_workspace_bytes() gives bitwise the
     result of the library's own; a smaller one is refused (EINVAL)."""
     import torch
-    wl = workloads.standard_workload("uniform" if kT else 1, n=300)
+    wl = workloads.standard_workload("uniform" if kT else "bands", n=300)
     H = dev(wl.hp)
     tol = 1e-9 if kT else wl.tol
     D0, e0, st0 = fdm.solve(H, wl.n_occ, kT, tol, prec, estimate_gap=0 if kT else 1)

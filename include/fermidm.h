@@ -93,6 +93,8 @@ typedef struct fdm_options {
                                step).  Bounds that turn out wrong make the expansion miss
                                n_occ or stall; the solve then repeats as plain SP2.  NaN
                                (default) = plain SP2                                           */
+    double mu_guess;        /* finite T: start of the mu search (e.g. the previous SCF step's mu);
+                               NaN (default) = the guess from the moments of Hp                */
     void *workspace;        /* optional caller-owned device memory of workspace_bytes          */
     size_t workspace_bytes; /* at least fdm_workspace_bytes(N, kT, precision)                  */
 } fdm_options;

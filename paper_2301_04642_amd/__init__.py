@@ -38,7 +38,8 @@ class fdm_options(ctypes.Structure):
                 ("timing", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("bounds", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32),
                 ("estimate_gap", ctypes.c_int32), ("homo", ctypes.c_double),
-                ("lumo", ctypes.c_double), ("workspace", ctypes.c_void_p),
+                ("lumo", ctypes.c_double), ("mu_guess", ctypes.c_double),
+                ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t)]
 
 

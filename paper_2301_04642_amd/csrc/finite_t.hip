@@ -251,14 +251,16 @@ int Ctx::solve_finite_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, d
     const int extra = opt.fd_extra_depth;
     const int pe = opt.precision;  // precision of the mu search
     split_prec = pe;
-    // Start: the uniform-density guess from the exact moments.  The Lanczos
+    // Start: the caller's guess (e.g. the previous SCF step's mu), else the
+    // uniform-density guess from the exact moments.  The Lanczos
     // Gauss quadrature of the spectral density (bounds = 1; one random start
     // vector, so its count carries a statistical error of ~sqrt(2 n_occ)
     // states) gives a second guess, tried once when the first Newton step
     // fails: it sees gaps in the spectrum that the uniform guess cannot.
     const double m1 = h.trH / (double)n;
     const double m2 = std::max(h.fro2H / (double)n - m1 * m1, 0.0);
-    double mu = m1 + sqrt(3.0 * m2) * (2.0 * n_occ / (double)n - 1.0);
+    double mu = std::isfinite(opt.mu_guess) ? opt.mu_guess
+                                            : m1 + sqrt(3.0 * m2) * (2.0 * n_occ / (double)n - 1.0);
     double mu_quad = NAN;
     if (ritz.size() >= 2) {
         const double tq = std::max(kT, 0.5 * (ritz.back() - ritz.front()) / (double)ritz.size());

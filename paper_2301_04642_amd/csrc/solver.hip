@@ -920,6 +920,7 @@ int fdm_options_default(fdm_options *opt) {
     opt->lanczos_steps = 16;
     opt->homo = NAN;
     opt->lumo = NAN;
+    opt->mu_guess = NAN;
     opt->estimate_gap = 0;
     return FDM_OK;
 }

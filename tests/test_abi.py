@@ -69,7 +69,7 @@ def test_options_default_and_strerror():
     assert o.fd_extra_depth == 7 and o.fd_final_fp64 == 1 and o.workspace is None
     assert o.bounds == 1 and o.lanczos_steps == 16
     assert o.homo != o.homo and o.lumo != o.lumo  # NaN: plain SP2
-    assert o.estimate_gap == 0
+    assert o.estimate_gap == 0 and o.mu_guess != o.mu_guess
     assert fdm.fdm_strerror(fdm.FDM_ENOCONV) == "iteration did not converge"
     assert fdm.fdm_strerror(12345) == "unknown status"
     assert fdm.library().fdm_options_default(None) == fdm.FDM_EINVAL

@@ -110,3 +110,17 @@ def test_solve_mixed_final_fp64(fdm, prec):
     """Low-precision mu search, one FP64 evaluation and the trace correction."""
     st = check_solve(fdm, workloads.standard_workload("uniform", n=400), prec)
     assert st.products[fdm.PRECISIONS[prec]] > 0 and st.products[0] > 0
+
+
+def test_mu_guess_from_a_previous_solve(fdm):
+    """Started from the mu of an earlier solve of the same matrix (an SCF
+    step), the search ends after one evaluation with the same result."""
+    wl = workloads.standard_workload("uniform", n=600)
+    H = dev(wl.hp)
+    D0, e0, st0 = fdm.solve(H, wl.n_occ, wl.kT, 1e-9, "fp64")
+    D1, e1, st1 = fdm.solve(H, wl.n_occ, wl.kT, 1e-9, "fp64", mu_guess=st0.mu)
+    print(f"[report] mu guess: evals {st0.mu_evals} -> {st1.mu_evals}, |dE|={abs(e1 - e0):.1e}",
+          flush=True)
+    assert st1.status == 0 and st1.mu_evals <= 2 < st0.mu_evals
+    assert abs(e1 - e0) <= 1e-9 and abs(st1.mu - st0.mu) <= 1e-9
+    assert float((D1 - D0).abs().max()) <= 1e-9

@@ -71,6 +71,15 @@ def test_e1_finite_t(fdm, e1, prec):
     assert st.status == 0
     assert abs(np.trace(d) - n_occ) <= 1e-8
     assert abs(e - e_ref) <= (1e-9 if prec == "fp64" else 1e-6)
+    # the next SCF step starts its search from this mu
+    _, e2, st2 = fdm.solve(dev(h), n_occ, kT, 1e-9 if prec == "fp64" else 1e-6, prec,
+                           mu_guess=st.mu)
+    print(f"[report]   from the previous mu: evals {st2.mu_evals} {st2.ms_total:.0f} ms "
+          f"|dE|={abs(e2 - e_ref):.2e}", flush=True)
+    # (the mixed form still searches in low precision, whose trace noise
+    # leaves its mu about 1e-3 kT from the FP64 one: one or two more)
+    assert st2.status == 0 and st2.mu_evals <= (2 if prec == "fp64" else 4)
+    assert abs(e2 - e_ref) <= (1e-9 if prec == "fp64" else 1e-6)
 
 
 # ---------------------------------------------------------------------------

@@ -62,7 +62,8 @@ def large(n):
 
 if __name__ == "__main__":
     if "--large" in sys.argv:
-        for n in (16384, 32768):
+        sizes = [int(a) for a in sys.argv[2:]] or [16384, 32768]
+        for n in sizes:
             large(n)
     else:
         main()

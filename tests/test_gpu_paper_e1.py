@@ -147,3 +147,47 @@ def test_e1_paper_sizes_zero_t(fdm, n):
         assert abs(e - e_ref) <= (1e-8 if prec == "fp64" else 1e-6)
         del D
     torch.cuda.empty_cache()
+
+
+def test_e1_n65536_zero_t_one_gpu(fdm):
+    """The paper's largest size, N = 65536 (§IV needed 2 nodes of 6 GPUs for
+    it), on one GPU: Hp, D and the FP16x3 working set take about 240 GB of
+    the 288 GB.  Plain SP2 and the accelerated form (HOMO/LUMO bounds 25%
+    inside the gap), checked against the banded-eigensolver reference."""
+    import torch
+    n = 65536
+    g = golden(n)
+    n_occ = int(g["zero_t_n_occ"][0])
+    e_ref = g["zero_t_band_energy"][0]
+    homo, lumo = g["homo_lumo"]
+    gap = lumo - homo
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    need = fdm.fdm_workspace_bytes(n, 0.0, fdm.FDM_FP16X3) + 2 * n * n * 8 + (4 << 30)
+    if total < need:
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of device memory, the device has "
+                    f"{total / 2**30:.0f}")
+    say("E1 build", n)
+    H = e1_device(n)
+    rows = np.sort(np.random.default_rng(n).choice(n, 2, replace=False))
+    for r in rows:
+        assert np.allclose(host(H[r:r + 1]), workloads.paper_e1_rows(n, r, r + 1),
+                           rtol=1e-15, atol=1e-16)
+    for extra in ({}, dict(homo=homo + 0.125 * gap, lumo=lumo - 0.125 * gap)):
+        say("E1 zero-T", n, "fp16x3", "az" if extra else "")
+        D, e, st = fdm.solve(H, n_occ, 0.0, 1e-8, "fp16x3", **extra)
+        tr = float(torch.trace(D))
+        dr = D[torch.from_numpy(rows).cuda()]
+        idem_rows = float(torch.linalg.norm(dr @ D - dr))
+        print(f"[report] E1 N={n} fp16x3{' A-Z' if extra else ''}: iters "
+              f"{st.iters_fp64_first}/{st.iters_low}/mcw{st.mcweeny_steps} products "
+              f"{sum(st.products)} |dE|={abs(e - e_ref):.2e} |dTr|={abs(tr - n_occ):.2e} "
+              f"idem={st.idempotency:.1e} rows idem={idem_rows:.1e} fallback={st.fallback_fp64} "
+              f"{st.ms_total:.0f} ms", flush=True)
+        assert st.status == 0
+        assert abs(tr - n_occ) <= 1e-8
+        assert st.idempotency <= 1e-8 and idem_rows <= 1e-8
+        assert abs(e - e_ref) <= 1e-6
+        del D
+    del H
+    torch.cuda.empty_cache()

@@ -808,14 +808,18 @@ int Ctx::solve_zero_t_once(const double *Hp, int64_t ldh, double *D, int64_t ldd
     int k64 = opt.k64;
     if (k64 < 0) {
         // FP64 steps while the Gershgorin over-estimate of the spectral width
-        // keeps the HOMO-LUMO gap of X tiny: ceil(log2(W_G / W_est)) with
+        // keeps the HOMO-LUMO gap of X tiny: ceil(log2(W / W_est)) with
         // W_est from the exact moments (2 sqrt(3) sigma, the width of a
-        // uniform spectrum).
+        // uniform spectrum).  Lanczos-tightened bounds are within a few % of
+        // the true width, so there only a width above 2 W_est counts
+        // (floor): the 20-band N = 4000 matrix (W / W_est = 1.02) reaches
+        // the same |dE| (2.2e-10 Ha) with its first step in FP32.
         const double mean = h.trH / (double)n;
         const double var = std::max(h.fro2H / (double)n - mean * mean, 1e-300);
         const double west = 2.0 * sqrt(3.0 * var);
         const double ratio = (h.emax - h.emin) / west;
-        k64 = ratio > 1.0 ? (int)ceil(log2(ratio)) : 0;
+        const double l2 = ratio > 1.0 ? log2(ratio) : 0.0;
+        k64 = (int)(opt.bounds == 1 ? floor(l2) : ceil(l2));
         // Larger N puts more states next to the gap and larger accumulation
         // errors into each product; measured on MI355X with FP32 bulk
         // products and Gershgorin bounds: N = 4000 passes |dE| <= 1e-6 with 5

@@ -196,10 +196,13 @@ __device__ __forceinline__ typename PT<P>::Acc mfma_frag(const u4_t &a, const u4
 }
 
 // 64-wide tiles are register-capped to four waves per SIMD (four blocks per
-// CU); 128-wide tiles run one wave per SIMD.
+// CU); 128-wide FP64 / FP32 tiles to two (two blocks per CU: 64 x 64 outputs
+// per wave, half the panel traffic per flop of a 64-wide tile); the other
+// 128-wide tiles run one wave per SIMD.
 template <int P, int BT>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(BT == 64 ? 4 : 1, BT == 64 ? 4 : 1)))
+__attribute__((amdgpu_waves_per_eu(BT == 64 ? 4 : ((P == P_F32 || P == P_F64) ? 2 : 1),
+                                    BT == 64 ? 4 : ((P == P_F32 || P == P_F64) ? 2 : 1))))
 void k_symprod(ProdArgs a) {
     if (a.done != nullptr && *a.done) return;
     using T = PT<P>;
@@ -287,13 +290,17 @@ void k_symprod(ProdArgs a) {
     // accumulation error then grows with the stage length (32) instead of
     // with N, which lowers the rounding floor of the low-precision SP2
     // iterates ~30x (the operand rounding is what remains).
-    // (64-wide tiles only: a 128-wide tile runs one wave per SIMD, where the
-    // extra VALU work serialises with the MFMAs and costs more than the
-    // FP64 refinement step it saves.)  The split forms carry 4x fewer MFMA
-    // cycles per stage, so there the fold (16 values x 4 VALU ops per lane)
-    // runs every 4 stages (128 deep): 5% faster products, same accuracy.
-    constexpr bool COMP = (P != P_F64) && BT == 64;
-    constexpr int FOLD = SPLIT ? 4 : 1;
+    // The split forms carry 4x fewer MFMA cycles per stage, so there the fold
+    // (16 values x 4 VALU ops per lane) runs every 4 stages (128 deep): 5%
+    // faster products, same accuracy.  The 128-wide FP32 tiles have no
+    // registers left for the Kahan term: they add each 128-deep partial sum
+    // plainly (rounding error growing with N/128 instead of N/4; the SP2
+    // floor at N = 16000 is 2.5e-5 against 2.2e-5 compensated and 1.9e-4
+    // with no fold); the other 128-wide tiles accumulate directly.
+    constexpr bool KAHAN = (P != P_F64) && BT == 64;
+    constexpr bool TWOLEVEL = (P == P_F32) && BT == 128;
+    constexpr bool COMP = KAHAN || TWOLEVEL;
+    constexpr int FOLD = (SPLIT || TWOLEVEL) ? 4 : 1;
     const int nk = a.kext / KST;
     Acc acc[FM][FM], cmp[FM][FM], part[FM][FM];
 #pragma unroll
@@ -341,11 +348,15 @@ void k_symprod(ProdArgs a) {
                     for (int j = 0; j < FM; ++j) {
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
-                            // Kahan: cmp holds the low-order part lost so far
-                            const float y = part[i][j][q] - cmp[i][j][q];
-                            const float t = acc[i][j][q] + y;
-                            cmp[i][j][q] = (t - acc[i][j][q]) - y;
-                            acc[i][j][q] = t;
+                            if constexpr (KAHAN) {
+                                // Kahan: cmp holds the low-order part lost so far
+                                const float y = part[i][j][q] - cmp[i][j][q];
+                                const float t = acc[i][j][q] + y;
+                                cmp[i][j][q] = (t - acc[i][j][q]) - y;
+                                acc[i][j][q] = t;
+                            } else {
+                                acc[i][j][q] += part[i][j][q];
+                            }
                         }
                         part[i][j] = Acc{0, 0, 0, 0};
                     }
@@ -363,7 +374,7 @@ void k_symprod(ProdArgs a) {
     // last one, in bounds and unused): a conditional load makes the
     // compiler's in-order vmcnt accounting wait for the newer set too, which
     // serialises the loads with the MFMAs.
-    if constexpr (P == P_F32 || P == P_F64) {
+    if constexpr ((P == P_F32 || P == P_F64) && BT == 64) {
         gload(0, ga0, gb0);
         gload(1, ga1, gb1);
         lstore(0, ga0, gb0);

@@ -212,16 +212,26 @@ Resources *thread_resources(int dev) {
 // ---------------------------------------------------------------------------
 int Ctx::tile_for(int prec) const {
     if (opt.tile == 64 || opt.tile == 128) return opt.tile;
-    // Measured on MI355X (N = 4000 / 16000): FP64 and FP32 are fastest with
-    // 64-wide tiles at every size (4 blocks per CU hide the MFMA latency).
-    // The split forms need the compensated accumulation of the 64-wide tiles
-    // at large N: with uncompensated 128-wide tiles (10% faster products at
-    // N = 16000) the FP16x3 iterate of the paper's N = 32768 matrix never got
-    // below tau in 100 steps (|dE| 4.5e-5 Ha), and N = 30000 ended at |dE|
-    // 1.4e-7 instead of 2.6e-10.  The single-pass 16-bit forms (reported,
-    // not gated) take 128-wide tiles once there are enough to fill the chip.
-    if (prec != P_F16 && prec != P_BF16) return 64;
+    // Measured on MI355X.
+    // FP32: 128-wide tiles (two waves per SIMD) once there are at least 16
+    // waves of them for the chip (N >= ~11500): 108 -> 128 TFLOP/s on a
+    // dense N = 16000 matrix, 121 -> 127 on the paper's N = 16384 one; even
+    // at N = 8192, far slower at N = 4000 (528 tiles).
+    // FP64: 64-wide tiles.  128-wide ones gain 8% on the dense N = 16000
+    // matrix (59.8 -> 64.9) but lose 12% on the paper's matrices at
+    // N = 12288 ... 32768 (74 -> 65), where the 64-wide tiles reach 95% of
+    // the FP64 peak.
+    // The split forms need the compensated accumulation of the 64-wide
+    // tiles at large N: with uncompensated 128-wide tiles (10% faster
+    // products at N = 16000) the FP16x3 iterate of the paper's N = 32768
+    // matrix never got below tau in 100 steps (|dE| 4.5e-5 Ha), and
+    // N = 30000 ended at |dE| 1.4e-7 instead of 2.6e-10.  The single-pass
+    // 16-bit forms (reported, not gated) take 128-wide tiles once there are
+    // enough to fill the chip.
     const int64_t t128 = ntiles_for(n, 128);
+    if (prec == P_F64) return 64;
+    if (prec == P_F32) return (t128 >= 16 * 256) ? 128 : 64;
+    if (prec != P_F16 && prec != P_BF16) return 64;
     return (t128 >= 4 * 256) ? 128 : 64;
 }
 

@@ -377,6 +377,8 @@ int Ctx::run_loop(int max_steps, const std::function<int(int)> &enqueue) {
 // bounds, so the sequence depends on (l0, h0) only and is fixed up front.
 void Ctx::build_az_schedule(double l, double h, int steps) {
     az_coef.assign(3 * (size_t)steps, 0.0);
+    az_gap.assign(steps + 1, 0.0);
+    az_gap[0] = h - l;
     az_branch.assign(steps, 0);
     for (int j = 0; j < steps; ++j) {
         const double eu = l, eo = 1.0 - h;
@@ -398,6 +400,7 @@ void Ctx::build_az_schedule(double l, double h, int steps) {
             l = 1.0 - k * (u - l) * (u - l);
             h = 1.0 - k * sh * sh;
         }
+        az_gap[j + 1] = h - l;
     }
 }
 
@@ -781,6 +784,7 @@ int Ctx::solve_zero_t_once(const double *Hp, int64_t ldh, double *D, int64_t ldd
     const int max_iter = opt.max_iter;
     az_coef.clear();
     az_branch.clear();
+    az_gap.clear();
     if (accel) {
         const double w = h.emax - h.emin;
         const double l0 = std::min(std::max((h.emax - opt.lumo) / w, 0.0), 1.0);
@@ -835,6 +839,17 @@ int Ctx::solve_zero_t_once(const double *Hp, int64_t ldh, double *D, int64_t ldd
         // products and Gershgorin bounds: N = 4000 passes |dE| <= 1e-6 with 5
         // FP64 steps (5.8e-8), N = 30000 needs 20 (4.8e-7; 16 gives 7.9e-6).
         if (n > 4000) k64 += (opt.bounds == 1 ? 1 : 5) * (int)ceil(log2((double)n / 4000.0));
+        // The accelerated polynomials open the gap of X more slowly in their
+        // first steps than X^2 / 2X - X^2 and much faster later; their FP64
+        // steps run until the known gap image h - l of X reaches 1e-3 N/4000
+        // (measured on the paper's matrix, FP16x3: at N = 32768, 4 FP64
+        // steps left |dE| = 7.4e-7 Ha, 12 steps (gap image 0.01) 1.9e-8).
+        if (!az_gap.empty()) {
+            const double g = 1e-3 * std::max(1.0, (double)n / 4000.0);
+            int j = 0;  // az_gap[j]: gap image after j steps
+            while (j + 1 < (int)az_gap.size() && az_gap[j] < g) ++j;
+            k64 = std::max(k64, j);
+        }
         k64 = std::min(std::max(k64, 0), 24);
     }
     // Leave low precision once every eigenvalue of X is within tau of 0 or 1

@@ -87,6 +87,7 @@ struct Ctx {
     // for SP2 step k at az_coef[3k..3k+2], and the form (1 = squaring form)
     std::vector<double> az_coef;
     std::vector<uint8_t> az_branch;
+    std::vector<double> az_gap;  // h - l before the first and after each accelerated step
     std::vector<Timed> timed;
 
     int tile_for(int prec) const;

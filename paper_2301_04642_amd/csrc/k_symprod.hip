@@ -196,13 +196,14 @@ __device__ __forceinline__ typename PT<P>::Acc mfma_frag(const u4_t &a, const u4
 }
 
 // 64-wide tiles are register-capped to four waves per SIMD (four blocks per
-// CU); 128-wide FP64 / FP32 tiles to two (two blocks per CU: 64 x 64 outputs
-// per wave, half the panel traffic per flop of a 64-wide tile); the other
-// 128-wide tiles run one wave per SIMD.
+// CU); 128-wide FP64, FP32 and split tiles to two (two blocks per CU: 64 x 64
+// outputs per wave, half the panel and LDS fragment traffic per flop of a
+// 64-wide tile); the single-pass 16-bit 128-wide tiles run one wave per SIMD.
 template <int P, int BT>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(BT == 64 ? 4 : ((P == P_F32 || P == P_F64) ? 2 : 1),
-                                    BT == 64 ? 4 : ((P == P_F32 || P == P_F64) ? 2 : 1))))
+__attribute__((amdgpu_waves_per_eu(
+    BT == 64 ? 4 : ((P == P_F32 || P == P_F64 || PT<P>::SPLIT) ? 2 : 1),
+    BT == 64 ? 4 : ((P == P_F32 || P == P_F64 || PT<P>::SPLIT) ? 2 : 1))))
 void k_symprod(ProdArgs a) {
     if (a.done != nullptr && *a.done) return;
     using T = PT<P>;
@@ -292,15 +293,16 @@ void k_symprod(ProdArgs a) {
     // iterates ~30x (the operand rounding is what remains).
     // The split forms carry 4x fewer MFMA cycles per stage, so there the fold
     // (16 values x 4 VALU ops per lane) runs every 4 stages (128 deep): 5%
-    // faster products, same accuracy.  The 128-wide FP32 tiles have no
-    // registers left for the Kahan term: they add each 128-deep partial sum
-    // plainly (rounding error growing with N/128 instead of N/4; the SP2
-    // floor at N = 16000 is 2.5e-5 against 2.2e-5 compensated and 1.9e-4
-    // with no fold); the other 128-wide tiles accumulate directly.
+    // faster products, same accuracy.  The 128-wide FP32 and split tiles
+    // have no registers left for the Kahan term: they add each 128-deep
+    // (FP32) or 256-deep (split) partial sum plainly (rounding error growing
+    // with N/128 instead of N/4; the FP32 SP2 floor at N = 16000 is 2.5e-5
+    // against 2.2e-5 compensated and 1.9e-4 with no fold, and FP16x3 keeps
+    // the compensated floor); the other 128-wide tiles accumulate directly.
     constexpr bool KAHAN = (P != P_F64) && BT == 64;
-    constexpr bool TWOLEVEL = (P == P_F32) && BT == 128;
+    constexpr bool TWOLEVEL = (P == P_F32 || SPLIT) && BT == 128;
     constexpr bool COMP = KAHAN || TWOLEVEL;
-    constexpr int FOLD = (SPLIT || TWOLEVEL) ? 4 : 1;
+    constexpr int FOLD = (SPLIT && BT == 128) ? 8 : ((SPLIT || TWOLEVEL) ? 4 : 1);
     const int nk = a.kext / KST;
     Acc acc[FM][FM], cmp[FM][FM], part[FM][FM];
 #pragma unroll

@@ -221,17 +221,16 @@ int Ctx::tile_for(int prec) const {
     // matrix (59.8 -> 64.9) but lose 12% on the paper's matrices at
     // N = 12288 ... 32768 (74 -> 65), where the 64-wide tiles reach 95% of
     // the FP64 peak.
-    // The split forms need the compensated accumulation of the 64-wide
-    // tiles at large N: with uncompensated 128-wide tiles (10% faster
-    // products at N = 16000) the FP16x3 iterate of the paper's N = 32768
-    // matrix never got below tau in 100 steps (|dE| 4.5e-5 Ha), and
-    // N = 30000 ended at |dE| 1.4e-7 instead of 2.6e-10.  The single-pass
-    // 16-bit forms (reported, not gated) take 128-wide tiles once there are
-    // enough to fill the chip.
+    // Split forms: 128-wide tiles at two waves per SIMD with the 256-deep
+    // fold once there are 2048 of them (N >= ~8100): 615 -> 753 TFLOP/s at
+    // N = 8192, 606 -> 907 at N = 16000, 673 -> 1010 on the paper's
+    // N = 32768 matrix, same SP2 floor.  (Without any fold they never got
+    // below tau there.)  The single-pass 16-bit forms (reported, not gated)
+    // take 128-wide tiles once there are enough to fill the chip.
     const int64_t t128 = ntiles_for(n, 128);
     if (prec == P_F64) return 64;
     if (prec == P_F32) return (t128 >= 16 * 256) ? 128 : 64;
-    if (prec != P_F16 && prec != P_BF16) return 64;
+    if (prec == P_F16X3 || prec == P_BF16X3) return (t128 >= 8 * 256) ? 128 : 64;
     return (t128 >= 4 * 256) ? 128 : 64;
 }
 

@@ -304,6 +304,7 @@ def main():
     mult = 3.0 if name_dom in ("fp16x3", "bf16x3") else 1.0
     achieved = mult * per_product_flops / (avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[name_dom]
+    traffic = measured_traffic(name_dom)   # HBM bytes per launch (rocprofv3 counters)
     forms_out = {}
     for form, r in res.items():
         st = r["stats"]
@@ -344,7 +345,9 @@ def main():
         "fp64_solves_per_s": round(res[ref_form]["solves_per_s"], 4),
         "roofline": {"bound": "mfma", "kernel": f"k_symprod<{name_dom}>",
                      "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": measured_traffic(name_dom),
+                     "frac": round(achieved / peak, 4), "traffic": traffic,
+                     "traffic_GB_per_s": (round(traffic / (avg_ms * 1e-3) / 1e9, 1)
+                                          if traffic else None),
                      "avg_launch_ms": round(avg_ms, 4),
                      "flops_per_launch": mult * per_product_flops},
         "forms": forms_out,

@@ -79,7 +79,8 @@ def test_uniform_n12000_finite_t_mixed(fdm):
     f, mu = den.occupations(wl.lam, wl.n_occ, wl.kT)
     e_ref = float(np.dot(f, wl.lam))
     print(f"[report] uniform-n12000: evals={st.mu_evals} depth={st.depth} mu={st.mu:.9f} (exact {mu:.9f}) "
-          f"|dE|={abs(e - e_ref):.2e} |dTr|={abs(np.trace(d) - wl.n_occ):.2e}", flush=True)
+          f"|dE|={abs(e - e_ref):.2e} |dTr|={abs(np.trace(d) - wl.n_occ):.2e} "
+          f"products fp64 {st.products[0]} fp16x3 {st.products[2]} {st.ms_total:.0f} ms", flush=True)
     assert st.status == 0
     assert abs(e - e_ref) <= 1e-6
     assert abs(np.trace(d) - wl.n_occ) <= 1e-6

@@ -17,12 +17,13 @@
 //    ti*BT.. of A and rows tj*BT.. of B (B symmetric, so B[k][j] = B[j][k]),
 //    whole 128-byte lines along k (one K stage of one row), staged into
 //    unpadded LDS rows with the 16-byte chunks XOR-swizzled by the row index
-//    (the fragment reads hit every bank equally: measured 1.5x faster than
-//    padded rows), double buffered with one barrier per stage and the next
-//    stage's loads in flight during the MFMAs.  The split forms and the
-//    128-wide tiles load straight into LDS (global_load_lds_dwordx4: no
-//    VGPR round trip, no ds_write); the 64-wide FP64 / FP32 tiles stage
-//    through two register sets, two stages ahead.
+//    (the fragment reads hit every bank equally: 1.5x the read rate of
+//    16-byte-padded rows in a probe; the 64-wide FP32 tiles keep the padded
+//    rows), double buffered with one barrier per stage and the next stage's
+//    loads in flight during the MFMAs.  The split forms and the 128-wide
+//    tiles load straight into LDS (global_load_lds_dwordx4: no VGPR round
+//    trip, no ds_write); the 64-wide FP64 / FP32 tiles stage through two
+//    register sets, two stages ahead.
 //  * Every lane reads a 16-byte fragment (row = lane % 16, k-chunk =
 //    lane / 16).  The k order inside a fragment is irrelevant because A and
 //    B use the same one: FP64 feeds 2 v_mfma_f64_16x16x4 per fragment, FP32
@@ -216,14 +217,17 @@ void k_symprod(ProdArgs a) {
     using Acc = typename T::Acc;
     constexpr bool HALF = T::HALF;
     constexpr bool SPLIT = T::SPLIT;
-    // LDS rows hold one K stage of one operand row.  FP64, FP32 and the split
-    // forms (hi chunks 0-3, lo chunks 4-7) stage the 128-byte global line as
-    // is, with chunk c of row r at slot c ^ (r & 7): the fragment reads
-    // (16 rows x 4 chunks per wave) then hit every bank equally.  The
-    // single-pass 16-bit forms round while staging into 64-byte rows padded
-    // by 16 bytes.
-    constexpr bool SWZ = !(HALF && !SPLIT);
-    constexpr int RSB = SWZ ? 128 : 80;            // LDS row stride (bytes)
+    // LDS rows hold one K stage of one operand row.  FP64 and the split forms
+    // (hi chunks 0-3, lo chunks 4-7), and every form staged straight into
+    // LDS, keep the 128-byte global line as is, with chunk c of row r at slot
+    // c ^ (r & 7): the fragment reads (16 rows x 4 chunks per wave) then hit
+    // every bank equally (no bank-conflict stalls in the counters).  The
+    // 64-wide FP32 tiles through registers keep rows padded by 16 bytes
+    // (1.4% faster there: 596 vs 605 us per product at N = 4000, where their
+    // LDS traffic is far from the bound), and the single-pass 16-bit forms
+    // round while staging into 64-byte rows padded by 16 bytes.
+    constexpr bool SWZ = DMA || SPLIT || P == P_F64;
+    constexpr int RSB = SWZ ? 128 : (HALF ? 80 : 144);   // LDS row stride (bytes)
     constexpr int PANEL = BT * RSB;                // bytes of one operand panel
     constexpr int KST = (sizeof(S) == 8) ? 16 : 32;  // k elements per stage (128 B of S)
     constexpr int EPC = 16 / sizeof(S);            // S elements per 16-byte chunk
@@ -282,6 +286,9 @@ void k_symprod(ProdArgs a) {
                 const int off = r * RSB + ((ch ^ (r & 7)) << 4);
                 *(u4_t *)(pa + off) = ga[u];
                 *(u4_t *)(pb + off) = gb[u];
+            } else if constexpr (!HALF) {
+                *(u4_t *)(pa + r * RSB + ch * 16) = ga[u];
+                *(u4_t *)(pb + r * RSB + ch * 16) = gb[u];
             } else {
                 // single-pass FP16 / BF16: round the FP32 master while staging
                 u2_t h, l;
@@ -553,15 +560,28 @@ void k_symprod(ProdArgs a) {
     }
 }
 
-// Direct-to-LDS staging for the split forms and the 128-wide tiles; the
-// 64-wide FP64 / FP32 tiles keep the register path, whose second register set
-// prefetches two stages ahead.
-template <int P, int BT>
-constexpr bool kDirectLds = (P == P_F64 || P == P_F32 || PT<P>::SPLIT) && (PT<P>::SPLIT || BT == 128);
+// Staging path (measured on MI355X, SP2 solves of the paper's matrix):
+//  * split forms, 64-wide tiles: direct to LDS (0.32 -> 0.26 ms per product
+//    at N = 4000);
+//  * split forms, 128-wide tiles: direct to LDS up to N ~ 18000 (1012 ->
+//    1137 TFLOP/s at N = 16384), through registers beyond, where the
+//    operands stream from HBM and the register path keeps more loads in
+//    flight (1042 vs 924 at N = 20480, 1056 vs 826 at N = 32768);
+//  * FP64 / FP32, 128-wide tiles: direct to LDS (FP32 130.0 -> 131.7 at
+//    N = 32768);
+//  * FP64 / FP32, 64-wide tiles: registers, two stages ahead.
+constexpr int64_t kSplitDirectMaxLd = 18432;
 
 template <int P, int BT>
 hipError_t launch_t(const ProdArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_symprod<P, BT, kDirectLds<P, BT>>), dim3(a.ntiles), dim3(256), 0, s, a);
+    constexpr bool ok = (P == P_F64 || P == P_F32 || PT<P>::SPLIT);
+    bool direct = false;
+    if constexpr (PT<P>::SPLIT) direct = (BT == 64) || a.ld <= kSplitDirectMaxLd;
+    else if constexpr (ok) direct = (BT == 128);
+    if (direct)
+        hipLaunchKernelGGL((k_symprod<P, BT, ok>), dim3(a.ntiles), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_symprod<P, BT, false>), dim3(a.ntiles), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -217,10 +217,10 @@ int Ctx::tile_for(int prec) const {
     // waves of them for the chip (N >= ~11500): 108 -> 128 TFLOP/s on a
     // dense N = 16000 matrix, 121 -> 127 on the paper's N = 16384 one; even
     // at N = 8192, far slower at N = 4000 (528 tiles).
-    // FP64: 64-wide tiles.  128-wide ones gain 8% on the dense N = 16000
-    // matrix (59.8 -> 64.9) but lose 12% on the paper's matrices at
-    // N = 12288 ... 32768 (74 -> 65), where the 64-wide tiles reach 95% of
-    // the FP64 peak.
+    // FP64: the same rule as FP32.  With direct-to-LDS staging the 128-wide
+    // tiles gain 10% on the dense N = 16000 matrix (65.0 -> 58.9 ms per
+    // product) and 4-5% on the paper's matrices (66.9 -> 63.9 ms at
+    // N = 16384, 68.1 -> 70.6 TFLOP/s at N = 32768).
     // Split forms: 128-wide tiles at two waves per SIMD with the 256-deep
     // fold once there are 2048 of them (N >= ~8100): 615 -> 753 TFLOP/s at
     // N = 8192, 606 -> 907 at N = 16000, 673 -> 1010 on the paper's
@@ -228,8 +228,7 @@ int Ctx::tile_for(int prec) const {
     // below tau there.)  The single-pass 16-bit forms (reported, not gated)
     // take 128-wide tiles once there are enough to fill the chip.
     const int64_t t128 = ntiles_for(n, 128);
-    if (prec == P_F64) return 64;
-    if (prec == P_F32) return (t128 >= 16 * 256) ? 128 : 64;
+    if (prec == P_F64 || prec == P_F32) return (t128 >= 16 * 256) ? 128 : 64;
     if (prec == P_F16X3 || prec == P_BF16X3) return (t128 >= 8 * 256) ? 128 : 64;
     return (t128 >= 4 * 256) ? 128 : 64;
 }

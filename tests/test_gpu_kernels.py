@@ -156,3 +156,35 @@ def test_band_energy(fdm, n):
     e, tr = fdm.fdm_band_energy(dev(h), dev(d))
     assert abs(e - (h * d).sum()) <= 1e-12 * np.abs(h * d).sum()
     assert abs(tr - np.trace(d)) <= 1e-12 * n
+
+
+@pytest.mark.parametrize("n", [18000, 18500])
+def test_large_tile128_products_sampled(fdm, n):
+    """128-wide products at full size, either side of the padded leading
+    dimension (18048 | 18560) where the split forms switch from direct-to-LDS
+    to register staging: 64 sampled entries of X^2 and their mirrors against
+    FP64 dot products of the same operands."""
+    import torch
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal((n, n), dtype=np.float32).astype(np.float64)
+    x += x.T
+    x *= 0.5 / np.sqrt(n)
+    X = dev(x)
+    C = torch.empty_like(X)
+    ii = rng.integers(0, n, 64)
+    jj = rng.integers(0, n, 64)
+    ref = np.einsum("ij,ij->i", x[ii], x[jj])
+    mag = np.einsum("ij,ij->i", np.abs(x[ii]), np.abs(x[jj]))
+    ti, tj = torch.from_numpy(ii).cuda(), torch.from_numpy(jj).cuda()
+    for prec in ("fp64", "fp32", "fp16x3", "bf16x3"):
+        say("large tile-128 product", prec, n)
+        fdm.fdm_sym_product(prec, X, X, None, C, 1.0, 0.0, 0.0, tile=128)
+        got = host(C[ti, tj])
+        assert np.array_equal(got, host(C[tj, ti])), "result must be exactly symmetric"
+        u_in, u_acc = PREC_U[prec]
+        tol = 4.0 * (2 * u_in + np.sqrt(n) * u_acc) * mag
+        if prec != "fp64":
+            tol += 6e-8 * np.abs(ref) + 8 * 6e-8 * np.abs(x).max()
+        err = np.abs(got - ref)
+        assert (err <= tol).all(), (prec, float(err.max()), float(tol[np.argmax(err - tol)]))
+    del X, C

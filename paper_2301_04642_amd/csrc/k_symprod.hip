@@ -327,21 +327,24 @@ void k_symprod(ProdArgs a) {
         }
     };
 
-    // FP32-accumulating forms sum each K stage in a fresh accumulator and
-    // fold it into the running sum with a compensated (Kahan) add: the
-    // accumulation error then grows with the stage length (32) instead of
-    // with N, which lowers the rounding floor of the low-precision SP2
-    // iterates ~30x (the operand rounding is what remains).
-    // The split forms carry 4x fewer MFMA cycles per stage, so there the fold
-    // (16 values x 4 VALU ops per lane) runs every 4 stages (128 deep): 5%
-    // faster products, same accuracy.  The 128-wide FP32 and split tiles
-    // have no registers left for the Kahan term: they add each 128-deep
-    // (FP32) or 256-deep (split) partial sum plainly (rounding error growing
-    // with N/128 instead of N/4; the FP32 SP2 floor at N = 16000 is 2.5e-5
-    // against 2.2e-5 compensated and 1.9e-4 with no fold, and FP16x3 keeps
-    // the compensated floor); the other 128-wide tiles accumulate directly.
-    constexpr bool KAHAN = (P != P_F64) && BT == 64;
-    constexpr bool TWOLEVEL = (P == P_F32 || SPLIT) && BT == 128;
+    // FP32-accumulating forms sum a run of K stages in a fresh accumulator
+    // and fold it into the running sum: the accumulation error then grows
+    // with N / run length instead of N, which lowers the rounding floor of
+    // the low-precision SP2 iterates (the operand rounding is what remains).
+    //  * FP32: a plain add of each 128-deep partial sum (4 stages).  On
+    //    64-wide tiles a Kahan-compensated fold of every 32-deep stage costs
+    //    64 VALU ops per lane and stage: 0.597 vs 0.542 ms per product at
+    //    N = 4000 for an SP2 floor of 1.11e-5 vs 1.30e-5 (one McWeeny step
+    //    either way; 1.9e-4 with no fold at N = 16000).
+    //  * Split forms, 64-wide tiles: Kahan-compensated fold every 4 stages
+    //    (128 deep; their stages carry 4x fewer MFMA cycles).
+    //  * Split forms, 128-wide tiles (no registers left for the Kahan term):
+    //    plain add of each 256-deep partial sum, which keeps the compensated
+    //    floor.
+    //  * Single-pass 16-bit forms: compensated fold of every stage on 64-wide
+    //    tiles, direct accumulation on 128-wide ones.
+    constexpr bool KAHAN = (P != P_F64 && P != P_F32) && BT == 64;
+    constexpr bool TWOLEVEL = (P == P_F32) || (SPLIT && BT == 128);
     constexpr bool COMP = KAHAN || TWOLEVEL;
     constexpr int FOLD = (SPLIT && BT == 128) ? 8 : ((SPLIT || TWOLEVEL) ? 4 : 1);
     const int nk = a.kext / KST;

@@ -336,17 +336,18 @@ void k_symprod(ProdArgs a) {
     //    64 VALU ops per lane and stage: 0.597 vs 0.542 ms per product at
     //    N = 4000 for an SP2 floor of 1.11e-5 vs 1.30e-5 (one McWeeny step
     //    either way; 1.9e-4 with no fold at N = 16000).
-    //  * Split forms, 64-wide tiles: Kahan-compensated fold every 4 stages
-    //    (128 deep; their stages carry 4x fewer MFMA cycles).
-    //  * Split forms, 128-wide tiles (no registers left for the Kahan term):
-    //    plain add of each 256-deep partial sum, which keeps the compensated
-    //    floor.
+    //  * Split forms: a plain add of each 256-deep partial sum (8 stages;
+    //    their stages carry 4x fewer MFMA cycles).  A Kahan fold every 128
+    //    deep on 64-wide tiles gave the same SP2 floor (8.2e-5 at N = 4000,
+    //    2.4e-5 at N = 6000) at 0.260 vs 0.241 ms per product; with no fold
+    //    the FP16x3 iterate of the paper's N = 32768 matrix never got below
+    //    tau.
     //  * Single-pass 16-bit forms: compensated fold of every stage on 64-wide
     //    tiles, direct accumulation on 128-wide ones.
-    constexpr bool KAHAN = (P != P_F64 && P != P_F32) && BT == 64;
-    constexpr bool TWOLEVEL = (P == P_F32) || (SPLIT && BT == 128);
+    constexpr bool KAHAN = (P != P_F64 && P != P_F32 && !SPLIT) && BT == 64;
+    constexpr bool TWOLEVEL = (P == P_F32) || SPLIT;
     constexpr bool COMP = KAHAN || TWOLEVEL;
-    constexpr int FOLD = (SPLIT && BT == 128) ? 8 : ((SPLIT || TWOLEVEL) ? 4 : 1);
+    constexpr int FOLD = SPLIT ? 8 : (TWOLEVEL ? 4 : 1);
     const int nk = a.kext / KST;
     Acc acc[FM][FM], cmp[FM][FM], part[FM][FM];
 #pragma unroll

@@ -852,8 +852,8 @@ int Ctx::solve_zero_t_once(const double *Hp, int64_t ldh, double *D, int64_t ldd
     }
     // Leave low precision once every eigenvalue of X is within tau of 0 or 1
     // (tau << 1/4 keeps each on its side).  The low-precision iterates floor
-    // near ||X^2 - X||_F ~ 1e-5 (FP32, compensated) to 1e-4 (split 16-bit
-    // forms) at N = 4000 (measured), and the quadratic step that takes the
+    // near ||X^2 - X||_F ~ 1e-5 (FP32) to 1e-4 (split 16-bit forms) at
+    // N = 4000 (measured), and the quadratic step that takes the
     // iterate below tau lands near that floor, so a lower tau only adds
     // low-precision steps; the stagnation guard ends the phase on the floor.
     double tau = opt.tau;

@@ -155,6 +155,7 @@ def serving(args):
         for kind in ("gapped", "metallic"):
             req = dict(id=100 * i + (kind == "metallic"), n=n, n_occ=n // 4,
                        kT=0.0 if kind == "gapped" else workloads.gen.KT_500K, seed=5_000_000 + 7 * i)
+            log(f"  template n={n} {kind}")
             wl = workloads.serving_workload(req)
             from oracle import density as den
             f, _ = den.occupations(wl.lam, wl.n_occ, wl.kT)
@@ -181,7 +182,9 @@ def serving(args):
             tickets.append((srv.submit(q["hp"], q["n_occ"], q["kT"], 1e-8), time.perf_counter() - t0))
         lat, worst = [], 0.0
         t_end = 0.0
-        for (t, t_sub), q in zip(tickets, reqs):
+        for k, ((t, t_sub), q) in enumerate(zip(tickets, reqs)):
+            if k % 4 == 0:
+                log(f"  collecting result {k} / {len(reqs)}")
             rc, d, e, st, times = srv.result(t, q["n"])
             assert rc == 0, rc
             worst = max(worst, abs(e - q["e_ref"]))
@@ -201,7 +204,9 @@ def serving(args):
     log("one at a time, fp64")
     H = None
     t0 = time.perf_counter()
-    for q in reqs:
+    for k, q in enumerate(reqs):
+        if k % 4 == 0:
+            log(f"  request {k} / {len(reqs)}")
         H = torch.from_numpy(q["hp"]).cuda()
         fdm.solve(H, q["n_occ"], q["kT"], 1e-8, "fp64")
     torch.cuda.synchronize()

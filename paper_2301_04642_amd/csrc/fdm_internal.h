@@ -82,7 +82,6 @@ struct ProdArgs {
     // one row is a single 128-byte line.
     const uint16_t *Ahl, *Bhl;
     uint16_t *Chl;
-    int64_t hl_off;         // unused (0)
 };
 
 // ---- launchers (k_symprod.hip, k_aux.hip) --------------------------------

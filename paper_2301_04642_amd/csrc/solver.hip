@@ -265,7 +265,6 @@ int Ctx::product(int prec, const void *A, const void *B, const void *E, void *C,
         a.Ahl = comp(A);
         a.Bhl = comp(B);
         a.Chl = comp(C);
-        a.hl_off = 0;
         if (!a.Ahl || !a.Bhl || !a.Chl) {
             set_error("internal: split operand outside the FP32 working buffers");
             return FDM_EHIP;

@@ -95,7 +95,8 @@ typedef struct fdm_options {
                                (default) = plain SP2                                           */
     double mu_guess;        /* finite T: start of the mu search (e.g. the previous SCF step's mu);
                                NaN (default) = the guess from the moments of Hp                */
-    void *workspace;        /* optional caller-owned device memory of workspace_bytes          */
+    void *workspace;        /* optional caller-owned device memory of workspace_bytes, 256-byte
+                               aligned (FDM_EINVAL otherwise)                                   */
     size_t workspace_bytes; /* at least fdm_workspace_bytes(N, kT, precision)                  */
 } fdm_options;
 

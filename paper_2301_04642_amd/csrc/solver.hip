@@ -128,6 +128,11 @@ int Resources::bind(const Layout &L, void *user_mem, size_t user_bytes, hipStrea
             set_error("workspace_bytes smaller than fdm_workspace_bytes()");
             return FDM_EINVAL;
         }
+        // the product kernels read whole 16-byte chunks of 128-byte rows
+        if ((uintptr_t)user_mem % 256 != 0) {
+            set_error("workspace must be 256-byte aligned");
+            return FDM_EINVAL;
+        }
         mem = (char *)user_mem;
     } else {
         if (!owned || cap < L.bytes) {

@@ -234,7 +234,8 @@ def test_low_precision_cap_falls_back_to_fp64(fdm):
 @pytest.mark.parametrize("prec,kT", [("fp64", 0.0), ("fp16x3", 0.0), ("fp32", 0.0016)])
 def test_caller_workspace(fdm, prec, kT):
     """A caller-owned workspace of fdm_workspace_bytes() gives bitwise the
-    result of the library's own; a smaller one is refused (EINVAL)."""
+    result of the library's own; a smaller or misaligned one is refused
+    (EINVAL)."""
     import torch
     wl = workloads.standard_workload("uniform" if kT else "bands", n=300)
     H = dev(wl.hp)
@@ -250,6 +251,13 @@ def test_caller_workspace(fdm, prec, kT):
         assert st1.homo_ub == st0.homo_ub and st1.lumo_lb == st0.lumo_lb
     rc, _, _ = fdm.fermi_dm_solve(H, wl.n_occ, kT, tol, torch.empty_like(H),
                                   _opts(fdm, prec, ws, nb - 256), raise_on_error=False)
+    assert rc == fdm.FDM_EINVAL
+    # a misaligned block is refused too
+    big = torch.empty(nb + 512, dtype=torch.uint8, device="cuda")
+    o = _opts(fdm, prec, big, nb)
+    o.workspace = big.data_ptr() + 16
+    rc, _, _ = fdm.fermi_dm_solve(H, wl.n_occ, kT, tol, torch.empty_like(H), o,
+                                  raise_on_error=False)
     assert rc == fdm.FDM_EINVAL
 
 

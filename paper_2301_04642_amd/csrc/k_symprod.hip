@@ -426,16 +426,22 @@ void k_symprod(ProdArgs a) {
     // serialises the loads with the MFMAs.
     if constexpr (DMA) {
         // Stage kt+1 streams into the other buffer while stage kt is
-        // multiplied; the barrier's vmcnt(0) completes it.
+        // multiplied.  A direct-to-LDS load counts on vmcnt until its data
+        // is in LDS: each wave waits for its own loads, then the barrier
+        // makes every wave's part of the stage visible.
+        auto stage_done = [&]() {
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), other counters untouched
+            __syncthreads();
+        };
         dload(0, 0);
-        __syncthreads();
+        stage_done();
         for (int kt = 0; kt < nk; kt += 2) {
             dload(kt + 1, 1);
             compute(0, kt);
-            __syncthreads();
+            stage_done();
             if (kt + 2 < nk) dload(kt + 2, 0);
             compute(1, kt + 1);
-            __syncthreads();
+            stage_done();
         }
     } else if constexpr ((P == P_F32 || P == P_F64) && BT == 64) {
         gload(0, ga0, gb0);

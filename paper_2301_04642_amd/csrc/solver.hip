@@ -230,11 +230,21 @@ int Ctx::tile_for(int prec) const {
     // fold once there are 2048 of them (N >= ~8100): 615 -> 753 TFLOP/s at
     // N = 8192, 606 -> 907 at N = 16000, 673 -> 1010 on the paper's
     // N = 32768 matrix, same SP2 floor.  (Without any fold they never got
-    // below tau there.)  The single-pass 16-bit forms (reported, not gated)
-    // take 128-wide tiles once there are enough to fill the chip.
+    // below tau there.)  Below that the 64-wide tiles win where both sizes
+    // leave the same number of waves of blocks (N = 4000: 2016 tiles in two
+    // waves of 1024 slots against 528 in two waves of 512), but where all
+    // 128-wide tiles fit in one wave of 512 slots and the 64-wide ones need
+    // well over one wave of 1024, the 128-wide ones are faster: 0.177 ->
+    // 0.162 ms at N = 3500, 0.243 -> 0.192 ms at N = 3968 (3000: 0.129 vs
+    // 0.133, 64-wide still ahead).  The single-pass 16-bit forms (reported,
+    // not gated) take 128-wide tiles once there are enough to fill the chip.
     const int64_t t128 = ntiles_for(n, 128);
     if (prec == P_F64 || prec == P_F32) return (t128 >= 16 * 256) ? 128 : 64;
-    if (prec == P_F16X3 || prec == P_BF16X3) return (t128 >= 8 * 256) ? 128 : 64;
+    if (prec == P_F16X3 || prec == P_BF16X3) {
+        const int64_t t64 = ntiles_for(n, 64);
+        const bool one_wave_128 = t128 <= 2 * 256 && t64 >= 1400;
+        return (t128 >= 8 * 256 || one_wave_128) ? 128 : 64;
+    }
     return (t128 >= 4 * 256) ? 128 : 64;
 }
 

@@ -175,6 +175,13 @@ def test_mixed_bands_small(fdm, prec):
     check_mixed(fdm, workloads.standard_workload("bands", n=1000), prec, bounds=0)
 
 
+@pytest.mark.parametrize("prec", ["fp16x3", "bf16x3"])
+def test_mixed_split_one_wave_128_tiles(fdm, prec):
+    """N = 3500: all 128-wide tiles fit in one wave of blocks, so the split
+    forms take them (below and above this window they take 64-wide ones)."""
+    check_mixed(fdm, workloads.standard_workload("bands", n=3500), prec)
+
+
 @pytest.mark.parametrize("prec", MIXED)
 def test_mixed_bands_lanczos(fdm, prec):
     check_mixed(fdm, workloads.standard_workload("bands", n=1000), prec, bounds=1)

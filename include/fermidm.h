@@ -109,7 +109,8 @@ typedef struct fdm_stats {
     int32_t mcweeny_steps;      /* zero T mixed: FP64 McWeeny steps                            */
     int32_t mu_evals;           /* finite T: Fermi-operator evaluations                        */
     int32_t depth;              /* finite T: doubling steps per evaluation                     */
-    int32_t tile;               /* product tile edge used                                       */
+    int32_t tile;               /* tile edge of the last product launch (64 or 128; each
+                                   precision picks its own from N)                             */
     int32_t products[FDM_NPREC];    /* product launches that ran, per precision                */
     uint64_t branch_bits[4];    /* SP2 branch of product k (bit k; 1 = X^2), k < 256           */
     double e_min, e_max;        /* spectral bounds of Hp used by the expansion                  */

@@ -33,6 +33,9 @@
  *    text of the last error of the calling thread is fdm_last_error().
  *  - One solve per stream at a time; calls on different streams from
  *    different host threads are independent.
+ *  - Environment: FDM_PROGRESS=k makes a solve print "[fdm] n=N step s
+ *    done" to stderr after every k-th completed step of each phase (for
+ *    solves that run for minutes); unset or 0, the library prints nothing.
  */
 #ifndef FERMIDM_H
 #define FERMIDM_H

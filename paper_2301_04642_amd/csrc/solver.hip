@@ -14,6 +14,8 @@
 // round trip, and at most one step per phase is launched after convergence
 // (those launches see the device "done" flag and return at once).
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -354,7 +356,19 @@ int Ctx::affine(int in_f32, const void *in, int64_t ldi, int out_f32, void *out,
 
 // Runs `enqueue(k)` for k = 0, 1, ... keeping exactly one step in flight
 // beyond the last one observed, until the device reports done.
+// FDM_PROGRESS=k (environment) prints a line to stderr after every k-th
+// completed step of a phase: long solves (minutes at N = 65536) show that
+// they advance.
+static int progress_every() {
+    static const int every = [] {
+        const char *v = getenv("FDM_PROGRESS");
+        return v ? std::max(0, atoi(v)) : 0;
+    }();
+    return every;
+}
+
 int Ctx::run_loop(int max_steps, const std::function<int(int)> &enqueue) {
+    const int every = progress_every();
     int rc = enqueue(0);
     if (rc) return rc;
     hipError_t e = hipEventRecord(r->ev[0], s);
@@ -368,6 +382,10 @@ int Ctx::run_loop(int max_steps, const std::function<int(int)> &enqueue) {
         }
         e = hipEventSynchronize(r->ev[(k - 1) & 1]);
         if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        if (every > 0 && k % every == 0) {
+            fprintf(stderr, "[fdm] n=%lld step %d done\n", (long long)n, k);
+            fflush(stderr);
+        }
         if (r->hm_host->done) return FDM_OK;
         if (k >= max_steps) break;
     }

@@ -20,8 +20,9 @@ than X^2 or 2X - X^2 do.  The paper gives no formulas; the reading used here
   next bounds: e.g. for the first form l' = (s / (1 - s))^2 and
   h' = ((h - s) / (1 - s))^2.  The bounds evolve independently of X, so the
   whole sequence of polynomials is fixed by (l_0, h_0).
-* Stop as in the plain expansion: when ||X_n^2 - X_n||_F <= tol, X_n is
-  returned (its square is the product that measured it).
+* Stop as in the plain expansion: when ||X_n^2 - X_n||_F <= tol and
+  |Tr X_n - N_occ| <= tol, X_n is returned (its square is the product that
+  measured the idempotency).
 """
 from __future__ import annotations
 
@@ -87,11 +88,12 @@ def azrfoe(h: np.ndarray, n_occ: float, homo: float, lumo: float, tol: float = 1
     n_done = 0
     eye = np.eye(n)
     for n_done in range(max_iter):
-        traces.append(float(np.trace(x)))
+        t = float(np.trace(x))
+        traces.append(t)
         p = x @ x
         e = float(np.linalg.norm(p - x))
         idem.append(e)
-        if e <= tol:
+        if e <= tol and abs(t - n_occ) <= tol:
             converged = True
             break
         (a, b, c), br, s, l, hb = step_polynomial(l, hb)
@@ -115,7 +117,7 @@ def scalar_iterations(lam: np.ndarray, n_occ: int, tol: float, e_min: float, e_m
         l, hb = start_bounds(e_min, e_max, homo, lumo)
     for it in range(max_iter):
         p = x * x
-        if float(np.sqrt(np.sum((p - x) ** 2))) <= tol:
+        if float(np.sqrt(np.sum((p - x) ** 2))) <= tol and abs(float(x.sum()) - n_occ) <= tol:
             return it
         if acc:
             (a, b, c), _, _, l, hb = step_polynomial(l, hb)

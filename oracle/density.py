@@ -79,6 +79,14 @@ def density_from_eig(q: np.ndarray, lam: np.ndarray, f: np.ndarray):
     return 0.5 * (d + d.T), float(np.dot(f, lam))
 
 
+def eigh_lapack(h: np.ndarray):
+    """Eigenpairs of symmetric h by LAPACK's dense symmetric eigensolver (a
+    library routine, used where the plain Jacobi sweep is too slow: N in the
+    thousands), sorted ascending.  Returns (w, V) with h ~= V diag(w) V^T."""
+    w, v = np.linalg.eigh(np.asarray(h, dtype=np.float64))
+    return w, v
+
+
 def density_matrix(h: np.ndarray, n_occ: float, kT: float = 0.0):
     """Reference density matrix of symmetric h by Jacobi eigendecomposition.
     Returns (D, E_band, mu, eigenvalues)."""
@@ -86,16 +94,6 @@ def density_matrix(h: np.ndarray, n_occ: float, kT: float = 0.0):
     f, mu = occupations(lam, n_occ, kT)
     d, e = density_from_eig(q, lam, f)
     return d, e, mu, lam
-
-
-def density_entries(q_rows, f: np.ndarray, rows, cols) -> np.ndarray:
-    """Selected entries D[rows[k], cols[k]] = sum_i f_i Q[r, i] Q[c, i], one by
-    one from explicit rows of the eigenbasis (q_rows(idx) -> rows of Q)."""
-    rows = np.asarray(rows)
-    cols = np.asarray(cols)
-    qr = q_rows(rows)
-    qc = q_rows(cols)
-    return np.einsum("ki,i,ki->k", qr, f, qc)
 
 
 def density_rows(q_rows, n: int, f: np.ndarray, rows, chunk: int = 4096) -> np.ndarray:

@@ -12,8 +12,9 @@ Readings where the paper is silent (each is listed in the design notes):
 * start: X_0 = (e_max I - H) / (e_max - e_min), which puts the spectrum in
   [0, 1] with occupied states near 1 (the paper writes X_0 = H);
 * branch: X^2 iff |Tr X^2 - N_occ| <= |Tr(2X - X^2) - N_occ| (ties -> X^2);
-* stop: when ||X_n^2 - X_n||_F <= tol the iterate X_n is returned (its
-  square is the product that measured it), else after max_iter products;
+* stop: when ||X_n^2 - X_n||_F <= tol and |Tr X_n - N_occ| <= tol the
+  iterate X_n is returned (its square is the product that measured the
+  idempotency), else after max_iter products;
 * McWeeny refinement X <- 3X^2 - 2X^3 for the final steps of the mixed forms.
 """
 from __future__ import annotations
@@ -65,7 +66,7 @@ def sp2(h: np.ndarray, n_occ: float, tol: float = 1e-10, max_iter: int = 100,
         p = x @ x
         e = float(np.linalg.norm(p - x))
         idem.append(e)
-        if e <= tol:
+        if e <= tol and abs(t - n_occ) <= tol:
             converged = True
             break
         branches.append(1 if sq else 0)
@@ -75,14 +76,16 @@ def sp2(h: np.ndarray, n_occ: float, tol: float = 1e-10, max_iter: int = 100,
     return x, info
 
 
-def mcweeny(x: np.ndarray, tol: float, max_steps: int = 8):
-    """X <- 3X^2 - 2X^3 until ||X^2 - X||_F <= tol.  Returns (X, steps, history)."""
+def mcweeny(x: np.ndarray, tol: float, max_steps: int = 8, n_occ=None):
+    """X <- 3X^2 - 2X^3 until ||X^2 - X||_F <= tol (and, when n_occ is given,
+    |Tr X - n_occ| <= tol as in the SP2 stop rule).  Returns (X, steps, history)."""
     hist = []
     for k in range(max_steps + 1):
         p = x @ x
         e = float(np.linalg.norm(p - x))
         hist.append(e)
-        if e <= tol or k == max_steps:
+        ok = e <= tol and (n_occ is None or abs(float(np.trace(x)) - n_occ) <= tol)
+        if ok or k == max_steps:
             return x, k, hist
         x = 3.0 * p - 2.0 * (p @ x)
     return x, max_steps, hist

@@ -299,6 +299,105 @@ def check_azrfoe_paper_counts(count=az.scalar_iterations):
     assert 24 <= acc <= 34, acc
 
 
+def check_sp2_stop_rule(sp2fn=sp2.sp2):
+    """The stop rule asks for both ||X^2 - X||_F <= tol and |Tr X - N_occ| <=
+    tol.  On a diagonal H with two clusters (+-0.1, n/4 occupied) and bounds
+    (-1, 1) every eigenvalue follows the scalar maps, so the first iterate
+    meeting both conditions is known; there the idempotency alone is met one
+    step earlier while the trace is still 1.8e-8 off."""
+    n, k, tol = 256, 64, 1e-8
+    lam = np.concatenate([np.full(k, -0.1), np.full(n - k, 0.1)])
+    x, info = sp2fn(np.diag(lam), k, tol=tol, bounds=(-1.0, 1.0))
+    s = (1.0 - lam) / 2.0
+    first = None
+    for it in range(100):
+        t, q = s.sum(), (s * s).sum()
+        p = s * s
+        if np.sqrt(((p - s) ** 2).sum()) <= tol and abs(t - k) <= tol:
+            first = it
+            break
+        s = p if abs(q - k) <= abs(2 * t - q - k) else 2 * s - p
+    assert info["converged"] and info["iterations"] == first, (info["iterations"], first)
+    assert abs(np.trace(x) - k) <= tol and np.linalg.norm(x @ x - x) <= tol
+    assert np.allclose(np.diag(x), s, atol=1e-15, rtol=0)
+
+
+def check_density_rows(rows_fn=den.density_rows, n=64):
+    """Rows of D = Q diag(f) Q^T built from row blocks of the eigenbasis equal
+    the rows of the Jacobi density matrix (an independent eigendecomposition),
+    at zero and finite temperature, with a block size that leaves a ragged
+    tail."""
+    for kind, kT in (("gapped", 0.0), ("uniform", 0.0016)):
+        wl = workloads.standard_workload(kind, n=n)
+        f, _ = den.occupations(wl.lam, wl.n_occ, kT)
+        d_jac, *_ = den.density_matrix(wl.hp, wl.n_occ, kT)
+        rows = np.array([0, 5, 17, n - 1])
+        got = rows_fn(wl.q_rows, n, f, rows, chunk=24)
+        assert got.shape == (rows.size, n)
+        assert np.abs(got - d_jac[rows]).max() < 1e-12, np.abs(got - d_jac[rows]).max()
+
+
+def check_kron_workload(make=workloads.make_workload):
+    """The Kronecker-Haar construction used above 8192 rows: Q orthogonal,
+    each column of Q an eigenvector of Hp with its eigenvalue, rows of Q by
+    q_rows equal to rows of the full matrix, and Jacobi recovers the
+    spectrum (n = 12 = 3 x 4 and n = 30 = 5 x 6)."""
+    for n in (12, 30):
+        rng = np.random.default_rng(n)
+        lam = rng.uniform(-1.0, 1.0, n)
+        wl = make("kron-pin", lam, n // 4, 0.0, 1e-10, 100 + n, kron=True)
+        assert wl.q is None and wl.q_factors is not None
+        q = wl.q_full()
+        assert np.abs(q.T @ q - np.eye(n)).max() < 1e-13
+        assert np.abs(wl.hp @ q - q * wl.lam[None, :]).max() < 1e-13
+        rows = np.array([0, 3, n - 1])
+        assert np.array_equal(wl.q_rows(rows), q[rows])
+        w, _ = jacobi_eigh(wl.hp)
+        assert np.abs(w - np.sort(lam)).max() < 1e-13
+
+
+def check_paper_e1_band(band=workloads.paper_e1_band):
+    """Band storage of the paper's matrix holds its diagonals (n = 200), and
+    the banded eigensolver on it gives the Jacobi spectrum of the dense
+    matrix (n = 96)."""
+    n, bw = 200, 80
+    h = workloads.paper_e1_matrix(n)
+    ab = band(n, bw)
+    assert ab.shape == (bw + 1, n)
+    for d in range(bw + 1):
+        assert np.array_equal(ab[bw - d, d:], np.diag(h, d)), d
+        assert np.all(ab[bw - d, :d] == 0.0)
+    w = den.band_storage_eigenvalues(band(96, bw))
+    wj, _ = jacobi_eigh(workloads.paper_e1_matrix(96))
+    assert np.abs(w - wj).max() < 1e-13
+
+
+def check_eps_metrics(e1=den.eps1, e2=den.eps2):
+    """Sec. III.C: eps1 = ||D - D_ref||_F / ||D_ref||_F, eps2 signed
+    (Tr(D H) - Tr(D_ref H)) / Tr(D_ref H).  Hand-computed cases."""
+    d_ref = np.diag([1.0, 1.0, 0.0])
+    d = np.diag([1.0, 0.9, 0.1])
+    assert abs(e1(d, d_ref) - 0.1) < 1e-15              # sqrt(0.02) / sqrt(2)
+    assert abs(e2(-9.9, -10.0) - (-0.01)) < 1e-15       # (-9.9 + 10) / -10
+    assert abs(e2(2.2, 2.0) - 0.1) < 1e-15
+
+
+def check_lapack_eigh(eigh=den.eigh_lapack, n=64):
+    """The library eigensolver used for references at large N agrees with
+    the plain Jacobi sweep and with a known spectrum."""
+    rng = np.random.default_rng(13)
+    g = rng.standard_normal((n, n))
+    h = 0.5 * (g + g.T)
+    w, v = eigh(h)
+    wj, vj = jacobi_eigh(h)
+    assert np.abs(w - wj).max() < 1e-12
+    assert np.abs(v[:, :20] @ v[:, :20].T - vj[:, :20] @ vj[:, :20].T).max() < 1e-11
+    wl = workloads.standard_workload("bands", n=n)
+    w, v = eigh(wl.hp)
+    assert np.abs(w - np.sort(wl.lam)).max() < 1e-13
+    assert np.abs((v * w) @ v.T - wl.hp).max() < 1e-13
+
+
 ALL_PINS = [
     check_jacobi_2x2, check_jacobi_toeplitz, check_jacobi_known_spectrum, check_jacobi_vs_lapack,
     check_density_invariants, check_density_vs_construction, check_shift_scale_and_permutation,
@@ -306,5 +405,6 @@ ALL_PINS = [
     check_sp2_diagonal, check_sp2_matches_definition, check_mcweeny,
     check_fd_recursion_closed_form, check_fd_recursion_dense, check_banded_eigenvalues,
     check_azrfoe_fold, check_azrfoe_diagonal, check_azrfoe_matches_definition,
-    check_azrfoe_paper_counts,
+    check_azrfoe_paper_counts, check_sp2_stop_rule, check_density_rows, check_kron_workload,
+    check_paper_e1_band, check_eps_metrics, check_lapack_eigh,
 ]

@@ -41,7 +41,9 @@ def test_fp64_matches_oracle(fdm, n, shrink):
     homo, lumo = gap_bounds(wl, shrink)
     d_ref, e_ref, _, _ = reference(wl)
     say("azrfoe fp64", n, shrink)
-    D, e, st = fdm.solve(dev(wl.hp), wl.n_occ, 0.0, 1e-11, "fp64", homo=homo, lumo=lumo)
+    # Gershgorin bounds, so that the oracle computes the same bounds itself
+    D, e, st = fdm.solve(dev(wl.hp), wl.n_occ, 0.0, 1e-11, "fp64", homo=homo, lumo=lumo,
+                         bounds=0)
     d = host(D)
     assert st.status == 0 and st.accelerated == 1
     assert np.linalg.norm(d - d_ref) <= 1e-10
@@ -49,13 +51,13 @@ def test_fp64_matches_oracle(fdm, n, shrink):
     assert abs(np.trace(d) - wl.n_occ) <= 1e-10
     assert np.array_equal(d, d.T)
     assert abs(den.band_energy(wl.hp, d) - e) <= 1e-10
-    x, info = az.azrfoe(wl.hp, wl.n_occ, homo, lumo, tol=1e-11, bounds=(st.e_min, st.e_max))
+    x, info = az.azrfoe(wl.hp, wl.n_occ, homo, lumo, tol=1e-11)
     assert np.linalg.norm(d - x) <= 1e-10
     assert abs(st.iters_fp64 - info["iterations"]) <= 1
     k = min(st.iters_fp64, info["iterations"])
     assert fdm.branch_list(st)[:k] == info["branches"][:k]
     # fewer products than plain SP2 on the same matrix
-    _, _, st_plain = fdm.solve(dev(wl.hp), wl.n_occ, 0.0, 1e-11, "fp64")
+    _, _, st_plain = fdm.solve(dev(wl.hp), wl.n_occ, 0.0, 1e-11, "fp64", bounds=0)
     print(f"[report] azrfoe fp64 n={n} shrink={shrink}: {st.iters_fp64} products "
           f"(oracle {info['iterations']}, plain SP2 {st_plain.iters_fp64})", flush=True)
     assert st.iters_fp64 < st_plain.iters_fp64

@@ -194,3 +194,71 @@ def test_mutant_azrfoe_branch_flipped(monkeypatch):
     from oracle import azrfoe as az
     monkeypatch.setattr(az, "step_polynomial", _az_step_variant(flip=True))
     assert _fails(pins.check_azrfoe_matches_definition, azfn=az.azrfoe, sizes=(16,))
+
+
+# --------------------------------------------------------------------------
+# planted mistakes in the full-size references and the metrics
+# --------------------------------------------------------------------------
+
+def test_mutant_sp2_stop_on_idempotency_only():
+    def bad_sp2(h, n_occ, tol=1e-10, max_iter=100, bounds=None):
+        lo, hi = bounds
+        x = sp2.initial_iterate(h, lo, hi)
+        it = 0
+        for it in range(max_iter):
+            t, s = np.trace(x), np.sum(x * x)
+            p = x @ x
+            if np.linalg.norm(p - x) <= tol:        # trace condition dropped
+                break
+            x = p if sp2.choose_square(t, s, n_occ) else 2 * x - p
+        return x, dict(iterations=it, converged=True)
+    assert _fails(pins.check_sp2_stop_rule, sp2fn=bad_sp2)
+
+
+def test_mutant_density_rows_without_occupations():
+    def bad(q_rows, n, f, rows, chunk=4096):
+        return den.density_rows(q_rows, n, np.ones_like(f), rows, chunk)
+    assert _fails(pins.check_density_rows, rows_fn=bad)
+
+
+def test_mutant_density_rows_chunk_offset():
+    def bad(q_rows, n, f, rows, chunk=4096):
+        qr = q_rows(np.asarray(rows)) * f[None, :]
+        out = np.empty((len(rows), n))
+        for c0 in range(0, n, chunk):
+            idx = np.arange(c0, min(n, c0 + chunk))
+            out[:, c0:c0 + idx.size] = qr @ q_rows(np.minimum(idx + 1, n - 1)).T
+        return out
+    assert _fails(pins.check_density_rows, rows_fn=bad)
+
+
+def test_mutant_kron_wrong_axis_order(monkeypatch):
+    import workloads.gen as gen
+
+    def bad_hp(qa, qb, lam_grid):
+        a, b = qa.shape[0], qb.shape[0]
+        t = np.einsum('ik,ck,jk->cij', qb, lam_grid, qb, optimize=True)
+        w = (qa[:, None, :] * qa[None, :, :]).reshape(a * a, a)
+        h = (w @ t.reshape(a, b * b)).reshape(a, a, b, b)
+        return np.ascontiguousarray(h).reshape(a * b, a * b)   # axes not interleaved
+    monkeypatch.setattr(gen, "_hp_from_kron", bad_hp)
+    assert _fails(pins.check_kron_workload, make=gen.make_workload)
+
+
+def test_mutant_e1_band_wrong_row_index():
+    def bad(n, bandwidth=80):
+        bw = min(bandwidth, n - 1)
+        ab = np.zeros((bw + 1, n))
+        for d in range(bw + 1):
+            j = np.arange(d, n)
+            ab[bw - d, d:] = np.exp(-0.5 * d) * np.sin(j + 1.0)   # column index, not min
+        return ab
+    assert _fails(pins.check_paper_e1_band, band=bad)
+
+
+def test_mutant_eps1_unnormalised():
+    assert _fails(pins.check_eps_metrics, e1=lambda d, r: float(np.linalg.norm(d - r)))
+
+
+def test_mutant_eps2_unsigned():
+    assert _fails(pins.check_eps_metrics, e2=lambda e, r: abs((e - r) / r))

@@ -53,7 +53,7 @@ extern "C" {
 #define FDM_ENOMEM (-2)     /* device allocation failed, or request above a budget    */
 #define FDM_ENOCONV (-3)    /* iteration cap or stagnation: D holds the last iterate   */
 #define FDM_EHIP (-4)       /* a HIP runtime error; see fdm_last_error()               */
-#define FDM_ENONFINITE (-5) /* Hp holds NaN or Inf                                     */
+#define FDM_ENONFINITE (-5) /* Hp holds NaN or Inf, or a product overflowed            */
 
 /* ---- precision of the bulk products ------------------------------------ */
 #define FDM_FP64 0    /* every product in FP64 MFMA (the plain method)                     */
@@ -80,10 +80,16 @@ typedef struct fdm_options {
     int32_t validate;       /* 1: reject an Hp that is not symmetric to 1e-12 relative (0)     */
     int32_t timing;         /* 1: time every product launch with HIP events (0)                */
     int32_t tile;           /* product tile edge: 0 = automatic, or 64 / 128                   */
-    int32_t bounds;         /* spectral bounds: 0 = Gershgorin discs; 1 (default) = Gershgorin
-                               tightened by a Lanczos estimate of the extreme eigenvalues
-                               (Ritz values widened by their residual bounds and 1% of the
-                               width, never outside the Gershgorin interval)                  */
+    int32_t bounds;         /* spectral bounds (Sec. II.C): 0 = Gershgorin discs; 1 (default)
+                               = Gershgorin tightened by a Lanczos estimate of the extreme
+                               eigenvalues (Ritz values widened by their residual bounds and
+                               1% of the width), widened by N^(1/64) * 1.03 about their centre
+                               and then certified: with A = (Hp - c I) / r for the interval
+                               c -+ r, ||A^32||_F^(1/32) (five FP16x3 products, with the
+                               rounding error of each bounded) must prove every eigenvalue of
+                               A inside [-1, 1]; otherwise the Gershgorin interval is used
+                               (stats.bounds_certified = -1).  Never outside the Gershgorin
+                               interval.                                                      */
     int32_t lanczos_steps;  /* Lanczos steps for bounds = 1 (default 16, at most 64)           */
     int32_t estimate_gap;   /* zero T: 1 = after the solve, estimate bounds on the HOMO and LUMO
                                eigenvalues for a later accelerated solve (stats homo_ub /
@@ -101,6 +107,22 @@ typedef struct fdm_options {
     void *workspace;        /* optional caller-owned device memory of workspace_bytes, 256-byte
                                aligned (FDM_EINVAL otherwise)                                   */
     size_t workspace_bytes; /* at least fdm_workspace_bytes(N, kT, precision)                  */
+    int32_t reltr_schedule; /* zero T: 1 = the paper's schedule (Sec. III.A, Sec. IV): SP2 in
+                               `precision` until RelTr <= reltr_switch, then FP64 SP2 until
+                               RelTr <= reltr_stop, where RelTr = |Tr X_n - Tr X_{n-1}| /
+                               |Tr X_{n-1}|; D is the last iterate (no idempotency stop, no
+                               McWeeny steps).  `tol` is not used (0)                           */
+    int32_t trfoe;          /* finite T: 1 = the truncated zero-temperature expansion of Sec.
+                               II.B.3, Eq. (2) (T-RFOE): `trfoe_depth` SP2 steps with trace-
+                               steered branches from X_0 and no mu search; D = X_m is a smeared
+                               step, not the Fermi operator (0)                               */
+    double reltr_switch;    /* 5e-4 */
+    double reltr_stop;      /* 5e-8 */
+    int32_t trfoe_depth;    /* 0 = from beta: the smallest m with (sqrt(5) - 1)^m >= beta (e_max -
+                               e_min) / 4, i.e. the slope of m SP2 steps on the unstable
+                               2-cycle of X^2 / 2X - X^2 (derivative sqrt(5) - 1 per step)
+                               matched to the Fermi function's slope beta / 4 at mu           */
+    int32_t reserved0;
 } fdm_options;
 
 /* Per-solve report (host memory, filled by fermi_dm_solve when non-NULL). */
@@ -143,6 +165,26 @@ typedef struct fdm_stats {
                                    unoccupied subspaces of D, widened by their residual
                                    bounds) to pass as homo / lumo to a later solve; NaN when
                                    not asked for or when they do not separate                 */
+    double rel_trace;           /* zero T: RelTr = |Tr X_n - Tr X_{n-1}| / |Tr X_{n-1}| of the
+                                   last SP2 product (the paper's convergence measure, Sec.
+                                   III.A)                                                     */
+    double idem_tail[8];        /* ||X^2 - X||_F measured by the last idem_tail_len (<= 8) SP2
+                                   or McWeeny products of the solve, oldest first             */
+    int32_t idem_tail_len;
+    int32_t bounds_certified;   /* 1 = the widened Lanczos bounds passed the certificate (see
+                                   fdm_options.bounds); 0 = Gershgorin bounds (bounds = 0, or
+                                   the widened interval was not narrower); -1 = the
+                                   certificate failed and the Gershgorin bounds were used      */
+    double lanczos_min, lanczos_max;  /* bounds = 1: the Lanczos estimate before widening     */
+    double cert_radius;         /* bounds = 1: the certified bound on max |lambda(A)| (<= 1 when
+                                   the certificate passed)                                    */
+    double phase_ms[4];         /* host wall time of: bounds; the first expansion phase (FP64
+                                   SP2, FP64-first SP2 steps, or the mu search in `precision`);
+                                   the low-precision SP2 phase (zero T) or the FP64 mu
+                                   evaluations (finite T); refinement and output (McWeeny,
+                                   canonical correction, energy, copy-out)                    */
+    int32_t trfoe_depth;        /* finite T with trfoe = 1: SP2 steps of the truncated expansion */
+    int32_t reltr_schedule;     /* zero T: 1 when the paper's RelTr schedule produced D        */
 } fdm_stats;
 
 /* Fills *opt with the defaults listed above.  Returns FDM_EINVAL if opt is NULL. */
@@ -208,7 +250,9 @@ int fdm_gershgorin(const double *H, int64_t N, int64_t ldh, double *out, int32_t
  * computed on the upper-triangular tiles only and mirrored, so C is exactly
  * symmetric.  A B is formed in `precision` (the FP16/BF16 forms round A and B
  * as described for FDM_FP16X3 .. FDM_FP16; the FP16 forms scale by 2^12 and
- * need |entries| <= 16).  The epilogue and the partial sums run in FP64.
+ * need |entries| < 65504 / 2^12 = 15.99, beyond which the scaled value
+ * overflows FP16).  The epilogue and the partial sums run in FP64.  Returns
+ * FDM_ENONFINITE (C then holds Inf/NaN) when a partial sum is not finite.
  *  A, B, E  device, N x N float64, leading dimension ld (E nullable = 0).
  *  C        device, N x N float64, leading dimension ld; may not alias A/B/E.
  *  sums     host double[3] (nullable): Tr C, ||C||_F^2, ||A B - E||_F^2.
@@ -247,11 +291,12 @@ typedef struct fdm_server fdm_server;
 
 typedef struct fdm_server_options {
     size_t budget_bytes;    /* device memory the server may hold for resident requests      */
-    int32_t max_active;     /* requests executing at once (each on its own stream; 8)        */
+    int32_t max_active;     /* requests executing at once (each on its own stream); 0 = 4    */
     int32_t precision;      /* default precision of submitted requests                      */
 } fdm_server_options;
 
-/* Creates a server on the current device.  Returns NULL on failure
+/* Creates a server on the current device (the caller selects it with
+ * hipSetDevice) with the budget and limits in *opt.  Returns NULL on failure
  * (fdm_last_error() says why). */
 fdm_server *fdm_server_create(const fdm_server_options *opt);
 
@@ -272,7 +317,14 @@ int fdm_poll(fdm_server *s, uint64_t ticket);
 int fdm_result(fdm_server *s, uint64_t ticket, double *D_out, int32_t out_on_host,
                int64_t ldd, double *E_band, fdm_stats *stats, double *times);
 
-/* Waits for all requests, frees every resource. */
+/* Device memory of the server (host size_t each, nullable): bytes held in
+ * blocks (in use or pooled for reuse; never above the budget), bytes reserved
+ * by admitted requests and results not yet collected, and pooled bytes. */
+int fdm_server_memory(fdm_server *s, size_t *held, size_t *reserved, size_t *pooled);
+
+/* Stops the server: requests that have not started are dropped, running ones
+ * finish, results not collected are discarded, and every resource is freed.
+ * No other call on `s` may be in progress or follow. */
 void fdm_server_destroy(fdm_server *s);
 
 #ifdef __cplusplus

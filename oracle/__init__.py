@@ -13,9 +13,11 @@ computes, written from the paper (arXiv 2301.04642):
 * ``fd``: the finite-temperature doubling recursion and its closed form.
 * ``azrfoe``: the accelerated zero-temperature expansion of Sec. II.B.2
   (shifted and scaled SP2 polynomials chosen from HOMO/LUMO bounds).
+* ``trfoe``: the truncated zero-temperature expansion used as a smeared step
+  at finite temperature (Sec. II.B.3, Eq. (2)).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  It shares no code with the GPU library
 and never calls it.
 """
-from . import azrfoe, density, fd, sp2  # noqa: F401
+from . import azrfoe, density, fd, sp2, trfoe  # noqa: F401

@@ -107,22 +107,29 @@ def azrfoe(h: np.ndarray, n_occ: float, homo: float, lumo: float, tol: float = 1
 
 
 def scalar_iterations(lam: np.ndarray, n_occ: int, tol: float, e_min: float, e_max: float,
-                      homo=None, lumo=None, max_iter: int = 200) -> int:
+                      homo=None, lumo=None, max_iter: int = 200, reltr_stop=None) -> int:
     """Iteration count of the expansion on a known spectrum (a diagonal H):
     with ``homo``/``lumo`` the accelerated polynomials, without them the plain
-    trace-chosen X^2 / 2X - X^2.  Same stop rule as ``azrfoe``."""
+    trace-chosen X^2 / 2X - X^2.  Same stop rule as ``azrfoe``, or with
+    ``reltr_stop`` the paper's relative-trace criterion (Sec. III.A): the
+    count of products up to the first iterate whose trace changed by at most
+    reltr_stop relative to the previous one."""
     x = (e_max - np.asarray(lam, dtype=np.float64)) / (e_max - e_min)
     acc = homo is not None
     if acc:
         l, hb = start_bounds(e_min, e_max, homo, lumo)
     for it in range(max_iter):
         p = x * x
-        if float(np.sqrt(np.sum((p - x) ** 2))) <= tol and abs(float(x.sum()) - n_occ) <= tol:
+        if (reltr_stop is None and float(np.sqrt(np.sum((p - x) ** 2))) <= tol
+                and abs(float(x.sum()) - n_occ) <= tol):
             return it
+        t = float(x.sum())
         if acc:
             (a, b, c), _, _, l, hb = step_polynomial(l, hb)
             x = a * p + b * x + c
         else:
-            t, s = float(x.sum()), float(p.sum())
+            s = float(p.sum())
             x = p if abs(s - n_occ) <= abs(2.0 * t - s - n_occ) else 2.0 * x - p
+        if reltr_stop is not None and abs(float(x.sum()) - t) / abs(t) <= reltr_stop:
+            return it + 1
     return -1

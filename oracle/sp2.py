@@ -47,10 +47,14 @@ def choose_square(trace: float, frob2: float, n_occ: float) -> bool:
 
 
 def sp2(h: np.ndarray, n_occ: float, tol: float = 1e-10, max_iter: int = 100,
-        bounds=None, x0=None):
+        bounds=None, x0=None, reltr_stop=None):
     """Plain float64 SP2.  Returns (D, info) with info holding the iteration
     count, the branch sequence (1 = X^2), the idempotency history and the
-    bounds.  ``x0`` (optional) replaces the scaled start."""
+    bounds.  ``x0`` (optional) replaces the scaled start.  With
+    ``reltr_stop`` the paper's criterion (Sec. III.A) replaces the
+    idempotency stop: the first iterate X_{n+1} whose relative trace change
+    |Tr X_{n+1} - Tr X_n| / |Tr X_n| is at most reltr_stop is returned, and
+    info["iterations"] counts the products that produced it."""
     e_min, e_max = gershgorin_bounds(h) if bounds is None else bounds
     x = initial_iterate(h, e_min, e_max) if x0 is None else np.array(x0, dtype=np.float64)
     branches = []
@@ -66,11 +70,16 @@ def sp2(h: np.ndarray, n_occ: float, tol: float = 1e-10, max_iter: int = 100,
         p = x @ x
         e = float(np.linalg.norm(p - x))
         idem.append(e)
-        if e <= tol and abs(t - n_occ) <= tol:
+        if reltr_stop is None and e <= tol and abs(t - n_occ) <= tol:
             converged = True
             break
         branches.append(1 if sq else 0)
         x = p if sq else 2.0 * x - p
+        if reltr_stop is not None and abs(float(np.trace(x)) - t) / abs(t) <= reltr_stop:
+            converged = True
+            n_done += 1
+            traces.append(float(np.trace(x)))
+            break
     info = dict(iterations=n_done, converged=converged, branches=branches, idempotency=idem,
                 traces=traces, bounds=(e_min, e_max))
     return x, info

@@ -27,7 +27,7 @@ PREC_NAMES = {v: k for k, v in PRECISIONS.items()}
 EXPORTS = ("fdm_options_default", "fdm_workspace_bytes", "fermi_dm_solve", "fdm_strerror",
            "fdm_last_error", "fdm_gershgorin", "fdm_sym_product", "fdm_band_energy",
            "fdm_fermi_operator", "fdm_server_create", "fdm_submit", "fdm_poll", "fdm_result",
-           "fdm_server_destroy")
+           "fdm_server_memory", "fdm_server_destroy")
 
 
 class fdm_options(ctypes.Structure):
@@ -40,7 +40,10 @@ class fdm_options(ctypes.Structure):
                 ("estimate_gap", ctypes.c_int32), ("homo", ctypes.c_double),
                 ("lumo", ctypes.c_double), ("mu_guess", ctypes.c_double),
                 ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("reltr_schedule", ctypes.c_int32),
+                ("trfoe", ctypes.c_int32), ("reltr_switch", ctypes.c_double),
+                ("reltr_stop", ctypes.c_double), ("trfoe_depth", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32)]
 
 
 class fdm_stats(ctypes.Structure):
@@ -58,7 +61,12 @@ class fdm_stats(ctypes.Structure):
                 ("mcweeny_idem", ctypes.c_double * 4), ("mcweeny_trace_err", ctypes.c_double * 4),
                 ("mu_hist", ctypes.c_double * 16), ("mu_trace_err", ctypes.c_double * 16),
                 ("fallback_fp64", ctypes.c_int32), ("reserved2", ctypes.c_int32),
-                ("homo_ub", ctypes.c_double), ("lumo_lb", ctypes.c_double)]
+                ("homo_ub", ctypes.c_double), ("lumo_lb", ctypes.c_double),
+                ("rel_trace", ctypes.c_double), ("idem_tail", ctypes.c_double * 8),
+                ("idem_tail_len", ctypes.c_int32), ("bounds_certified", ctypes.c_int32),
+                ("lanczos_min", ctypes.c_double), ("lanczos_max", ctypes.c_double),
+                ("cert_radius", ctypes.c_double), ("phase_ms", ctypes.c_double * 4),
+                ("trfoe_depth", ctypes.c_int32), ("reltr_schedule", ctypes.c_int32)]
 
     def as_dict(self):
         d = {}
@@ -113,6 +121,9 @@ def _load():
         "fdm_poll": (ctypes.c_int, [VP, ctypes.c_uint64]),
         "fdm_result": (ctypes.c_int, [VP, ctypes.c_uint64, P, I32, I64, ctypes.POINTER(D),
                                       ctypes.POINTER(fdm_stats), ctypes.POINTER(D)]),
+        "fdm_server_memory": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_size_t),
+                                             ctypes.POINTER(ctypes.c_size_t),
+                                             ctypes.POINTER(ctypes.c_size_t)]),
         "fdm_server_destroy": (None, [VP]),
     }
     for name, (res, args) in sig.items():
@@ -300,6 +311,13 @@ class Server:
         rc = _lib.fdm_result(self._s, ticket, ctypes.c_void_p(d.ctypes.data), 1, n,
                              ctypes.byref(e), ctypes.byref(st), times)
         return rc, d, e.value, st, list(times)
+
+    def memory(self):
+        """(held, reserved, pooled) device bytes."""
+        h, r, p = ctypes.c_size_t(0), ctypes.c_size_t(0), ctypes.c_size_t(0)
+        _check(_lib.fdm_server_memory(self._s, ctypes.byref(h), ctypes.byref(r), ctypes.byref(p)),
+               "fdm_server_memory")
+        return h.value, r.value, p.value
 
     def close(self):
         if self._s:

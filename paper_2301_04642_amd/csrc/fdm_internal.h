@@ -23,13 +23,29 @@ constexpr int kKStep = 64;  // K extent granule: two stages of every precision
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// Product tiles are listed in bands of this many tile rows (see upper_tiles).
+constexpr int kTileBand = 8;
+
+// Tile edge (64 or 128) of a product of size n in precision prec; forced = 64
+// or 128 overrides the measured choice.
+int choose_tile(int64_t n, int prec, int forced);
+
 // Decide-kernel modes (what the partial sums of the preceding launch mean).
+// Phase flags of DevState::switch_mode above the low three bits (which say
+// 0 = plain phase, 1 = low-precision phase left at tau, 2 = FP64-first
+// steps):
+constexpr int kGuard = 8;      // end the phase when ||X||^2 > Tr X + 0.5 (an eigenvalue
+                               // of X outside [0, 1]) or a sum is not finite
+constexpr int kRelTrStop = 16; // stop when RelTr <= tau instead of the idempotency rule
+constexpr int kFixedSteps = 32;// run exactly max_iter products (truncated expansion)
+
 enum DecideMode : int {
     D_INIT = 0,     // partials: Tr X, ||X||^2 of a new iterate; resets the phase
     D_SP2 = 1,      // partials of an SP2 product: Tr X+, ||X+||^2, ||X^2 - X||^2
     D_MCW_T = 2,    // partials of T = X X with E = X: ||X^2 - X||^2 in slot 2
     D_MCW_OUT = 3,  // partials of X' = 3T - 2TX
     D_SUMS = 4,     // plain reduction of (slot0, slot1, slot2) into st->sums
+    D_CERT = 5,     // slot1 (a squared Frobenius norm) appended to st->cert
 };
 
 // Device-resident solver state: every branch and stop decision is taken on
@@ -54,6 +70,11 @@ struct DevState {
     int32_t gprod;                   // global SP2 product counter (branch bits)
     uint64_t bits[4];
     double mcw_idem[4], mcw_trerr[4];  // FP64 McWeeny checks: ||X^2 - X||, |Tr X - n_occ|
+    double reltr;                    // |Tr X_n - Tr X_{n-1}| / |Tr X_{n-1}| of the last SP2 step
+    double idem_ring[8];             // last measured ||X^2 - X||_F values (ring, nring entries)
+    int32_t nring;
+    int32_t ncert;                   // entries of cert[] written since the last reset
+    double cert[8];                  // D_CERT: ||M_k||_F^2 of the bound certificate's powers
 };
 
 // What the host polls: written by the decide kernel into mapped pinned memory.

@@ -239,14 +239,64 @@ int Ctx::canonical_correction(void *dm, double tr, double trdd, double *mu, void
     return FDM_OK;
 }
 
+// The truncated zero-temperature expansion used as a smeared step (T-RFOE,
+// Sec. II.B.3, Eq. (2)): m SP2 steps from X_0 = (e_max I - H)/(e_max - e_min)
+// with the branch steered by the traces towards the (fractional) electron
+// count, stopped after m steps; D = X_m.  The paper ties m to beta only
+// qualitatively (more steps at lower temperature).  Here m is the smallest
+// depth whose slope at the Fermi level matches the Fermi function's,
+// beta / 4 per Hartree: along the unstable 2-cycle of x^2 / 2x - x^2 (the
+// points (3 - sqrt 5)/2 and (sqrt 5 - 1)/2, near which the trace-steered
+// iteration keeps the Fermi level) each step multiplies the slope by
+// sqrt(5) - 1, and X_0 has slope 1 / (e_max - e_min).
+int Ctx::solve_trfoe(const double *Hp, int64_t ldh, double *D, int64_t ldd, double *E_band) {
+    int m = opt.trfoe_depth;
+    if (m <= 0) {
+        const double need = (stats.e_max - stats.e_min) / (4.0 * kT);
+        m = need > 1.0 ? (int)ceil(log(need) / log(sqrt(5.0) - 1.0)) : 1;
+    }
+    m = std::min(std::max(m, 1), 255);
+    stats.trfoe_depth = m;
+    stats.mu = NAN;
+    const int prec = opt.precision;
+    const bool lo = prec != P_F64;
+    const size_t mm = (size_t)r->lay.np * r->lay.ld;
+    void *b0 = lo ? (void *)r->x32 : (void *)r->x64;
+    void *b1 = lo ? (void *)(r->x32 + mm) : (void *)(r->x64 + mm);
+    int rc = set_params(0.0, m, 0, 1);
+    if (rc) return rc;
+    int np = 0;
+    rc = affine(0, Hp, ldh, lo ? 1 : 0, b0, 0, 0, 1, &np);
+    if (rc) return rc;
+    rc = decide(D_INIT, np, 4);
+    if (rc) return rc;
+    phase_done(0);
+    void *res = nullptr;
+    int it = 0;
+    rc = sp2_phase(prec, b0, b1, m, kFixedSteps, 0.0, -1, &res, &it);
+    if (rc) return rc;
+    phase_done(1);
+    if (lo)
+        stats.iters_low = it;
+    else
+        stats.iters_fp64 = it;
+    stats.idempotency = r->hm_host->idem;
+    return finish(Hp, ldh, res, lo ? 1 : 0, D, ldd, E_band);
+}
+
 int Ctx::solve_finite_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, double *E_band) {
     DevState h;
     int rc = bounds(Hp, ldh, &h);
     if (rc) return rc;
     if (opt.bounds == 1 && h.emax > h.emin) {
-        rc = refine_bounds(Hp, ldh, &h);
+        rc = tight_bounds(Hp, ldh, &h);
         if (rc) return rc;
     }
+    if (opt.trfoe) {
+        split_prec = opt.precision;
+        return solve_trfoe(Hp, ldh, D, ldd, E_band);
+    }
+    phase_done(0);
     const double beta = 1.0 / kT;
     const int extra = opt.fd_extra_depth;
     const int pe = opt.precision;  // precision of the mu search
@@ -356,6 +406,7 @@ int Ctx::solve_finite_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, d
         // noise of FP32-class products); its result is not checked
         rc = search(pe, 1e-4, &converged);
         if (rc) return rc;
+        phase_done(1);
         if (!opt.fd_final_fp64) {
             // low precision end to end (reported, not gated): promote D
             int np = 0;
@@ -380,6 +431,7 @@ int Ctx::solve_finite_t(const double *Hp, int64_t ldh, double *D, int64_t ldd, d
         }
         rc = search(P_F64, 1e-3, &converged);
         if (rc) return rc;
+        phase_done(pe == P_F64 ? 1 : 2);
     }
     stats.mu_evals = evals;
     stats.depth = depth;

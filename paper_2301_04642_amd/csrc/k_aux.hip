@@ -397,44 +397,57 @@ __global__ __launch_bounds__(256) void k_decide(DevState *st, HostMirror *hm,
         case D_SP2: {
             // s0, s1: Tr and ||.||^2 of X_{n+1}; s2 = ||X_n^2 - X_n||^2.
             const int n = st->iter;
-            const int sm = st->switch_mode & 7;   // bit 3: divergence guard
+            const int flags = st->switch_mode;
+            const int sm = flags & 7;
             const double idem = sqrt(s2);
             const double two_back = st->idem_hist[1];  // idempotency of X_{n-2}
             st->idem_hist[0] = st->idem_hist[1];
             st->idem_hist[1] = st->idem;
             st->idem = idem;
+            st->idem_ring[st->nring & 7] = idem;
+            st->nring += 1;
             st->executed = n + 1;
+            // relative trace change of X_{n+1} against X_n (Sec. III.A)
+            const double reltr = fabs(s0 - st->trace) / fmax(fabs(st->trace), 1e-300);
+            st->reltr = reltr;
             // Below 0.1 every eigenvalue is within ~0.1 of 0 or 1 and two SP2
             // steps shrink the error at least 2.5x; a smaller gain means the
             // iteration sits on its rounding floor.
             const bool stagnant = idem < 0.1 && idem >= 0.8 * two_back;
-            const bool advance_bit = true;
             // X_{n+1} has left [0, 1] (||X||^2 > Tr X needs eigenvalues
-            // outside it; only shifted polynomials built from wrong HOMO/LUMO
-            // bounds can do that): give up before it overflows
-            if ((st->switch_mode & 8) && (!(idem < INFINITY) || !(s1 <= s0 + 0.5))) {
+            // outside it): give up before it overflows
+            if ((flags & kGuard) && (!(idem < INFINITY) || !(s1 <= s0 + 0.5))) {
                 st->done = 1;
                 st->result_iter = n;
                 st->status = FDM_ENOCONV;
                 break;
             }
-            // converged: idempotent and holding n_occ electrons (st->trace is
-            // still Tr X_n here)
-            if (idem <= st->tol && fabs(st->trace - st->n_occ) <= st->tol) {
-                st->done = 1;
-                st->result_iter = n;
-                break;
+            if (flags & kFixedSteps) {
+                // a truncated expansion runs exactly max_iter products
+            } else if (flags & kRelTrStop) {
+                if (reltr <= st->tau) {
+                    st->done = 1;
+                    st->result_iter = n + 1;
+                }
+            } else {
+                // converged: idempotent and holding n_occ electrons
+                // (st->trace is still Tr X_n here)
+                if (idem <= st->tol && fabs(st->trace - st->n_occ) <= st->tol) {
+                    st->done = 1;
+                    st->result_iter = n;
+                    break;
+                }
+                if (sm == 1 && (idem <= st->tau || stagnant)) {
+                    st->done = 1;
+                    st->result_iter = n + 1;
+                } else if (sm != 1 && stagnant) {
+                    st->done = 1;
+                    st->result_iter = n;
+                    st->status = FDM_ENOCONV;
+                    break;
+                }
             }
-            if (sm == 1 && (idem <= st->tau || stagnant)) {
-                st->done = 1;
-                st->result_iter = n + 1;
-            } else if (sm != 1 && stagnant) {
-                st->done = 1;
-                st->result_iter = n;
-                st->status = FDM_ENOCONV;
-                break;
-            }
-            if (advance_bit && st->gprod < 256)
+            if (st->gprod < 256)
                 st->bits[st->gprod >> 6] |= (uint64_t)(st->sigma & 1) << (st->gprod & 63);
             st->gprod += 1;
             st->iter = n + 1;
@@ -444,13 +457,15 @@ __global__ __launch_bounds__(256) void k_decide(DevState *st, HostMirror *hm,
             if (!st->done && st->iter >= st->max_iter) {
                 st->done = 1;
                 st->result_iter = st->iter;
-                if (sm == 0) st->status = FDM_ENOCONV;
+                if (sm == 0 && !(flags & kFixedSteps)) st->status = FDM_ENOCONV;
             }
             break;
         }
         case D_MCW_T: {
             const double idem = sqrt(s2);
             st->idem = idem;
+            st->idem_ring[st->nring & 7] = idem;
+            st->nring += 1;
             st->executed += 1;
             if (st->iter < 4) {
                 st->mcw_idem[st->iter] = idem;
@@ -472,6 +487,10 @@ __global__ __launch_bounds__(256) void k_decide(DevState *st, HostMirror *hm,
             st->trace = s0;
             st->fro2 = s1;
             break;
+        case D_CERT:
+            if (st->ncert < 8) st->cert[st->ncert] = s1;
+            st->ncert += 1;
+            break;
         case D_SUMS:
         default:
             st->sums[0] = s0;
@@ -480,14 +499,18 @@ __global__ __launch_bounds__(256) void k_decide(DevState *st, HostMirror *hm,
             break;
     }
     if (hm != nullptr) {
-        hm->done = st->done;
-        hm->iter = st->iter;
-        hm->result_iter = st->result_iter;
-        hm->executed = st->executed;
-        hm->status = st->status;
-        hm->sigma = st->sigma;
-        hm->idem = st->idem;
-        hm->trace = st->trace;
+        // The host polls `done` and then reads the other fields: they are
+        // written first and made visible before `done` is.
+        volatile HostMirror *vh = hm;
+        vh->iter = st->iter;
+        vh->result_iter = st->result_iter;
+        vh->executed = st->executed;
+        vh->status = st->status;
+        vh->sigma = st->sigma;
+        vh->idem = st->idem;
+        vh->trace = st->trace;
+        __threadfence_system();
+        vh->done = st->done;
         __threadfence_system();
     }
 }
@@ -502,6 +525,9 @@ __global__ void k_set_params(DevState *st, double n_occ, double tol, double tau,
     st->max_iter = max_iter;
     st->switch_mode = switch_mode;
     if (reset_all) {
+        st->ncert = 0;
+        st->nring = 0;
+        st->reltr = 0.0;
         st->gprod = 0;
         st->bits[0] = st->bits[1] = st->bits[2] = st->bits[3] = 0;
         st->done = 0;

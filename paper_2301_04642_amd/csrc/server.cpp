@@ -5,17 +5,18 @@
 // footprint (Hp + D + solver workspace, all proportional to N^2) fits in the
 // remaining budget; requests that arrive while others run join immediately,
 // and their kernels overlap on the device because every executor owns its
-// own stream.  Device blocks come from a caching allocator (so no hipFree,
-// which would synchronise the whole device, sits on the hot path).  Each
-// solve is deterministic (fixed tile order, fixed-order reductions, tile
-// shape chosen from N only), so a request's result does not depend on what
-// else is running.
+// own stream.  Device blocks come from a pool of size classes whose held
+// bytes (in use and pooled) stay within the budget.  Each solve is
+// deterministic (fixed tile order, fixed-order reductions, tile shape chosen
+// from N only), so a request's result does not depend on what else is
+// running.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <iterator>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -42,61 +43,75 @@ struct Request {
     double e_band = 0;
     fdm_stats stats;
     int status = 1;  // 1 pending, else solve status
+    bool collecting = false;  // an fdm_result call is copying D out
     double t_submit = 0, t_start = 0, t_finish = 0;
 };
 
-// Size-keyed cache of device blocks.  Blocks are only returned to HIP when
-// the budget needs the room.
-class BlockCache {
+// Device blocks come in size classes (eight per octave above 1 MiB, so at
+// most 12.5% is lost to rounding; multiples of 64 KiB below), and a freed
+// block stays in the pool of its class for the next request of a similar
+// size.  Every held byte -- blocks in use and pooled ones -- counts against
+// the server's budget: before a new block is allocated, pooled blocks are
+// evicted until the held bytes plus the new block fit.  Admission reserves a
+// request's footprint in class sizes, so the blocks in use never exceed the
+// reservations and eviction can always make room.  Eviction and allocation
+// run outside the server mutex (hipFree can wait for the device).
+size_t size_class(size_t bytes) {
+    const size_t kSmall = (size_t)1 << 20, kGran = (size_t)1 << 16;
+    if (bytes <= kSmall) return (bytes + kGran - 1) / kGran * kGran;
+    int e = 63 - __builtin_clzll((unsigned long long)bytes);
+    const size_t step = (size_t)1 << (e - 3);
+    return (bytes + step - 1) / step * step;
+}
+
+class BlockPool {
    public:
-    void *get(size_t bytes) {
-        auto it = free_.lower_bound(bytes);
-        if (it != free_.end() && it->first <= bytes + bytes / 8) {
-            void *p = it->second;
-            free_.erase(it);
-            return p;
-        }
-        void *p = nullptr;
-        if (hipMalloc(&p, bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            trim_all();
-            if (hipMalloc(&p, bytes) != hipSuccess) {
-                (void)hipGetLastError();
-                return nullptr;
-            }
-        }
-        sizes_[p] = bytes;
-        held_ += bytes;
+    // A pooled block of exactly this class, or nullptr.
+    void *take(size_t cls) {
+        auto it = free_.find(cls);
+        if (it == free_.end()) return nullptr;
+        void *p = it->second;
+        free_.erase(it);
+        pooled_ -= cls;
         return p;
     }
+    // Makes room for `need` more held bytes under `budget`: pooled blocks
+    // (largest first) move to *evict, to be freed by the caller outside the
+    // lock; the new bytes are counted as held at once.
+    bool reserve(size_t need, size_t budget, std::vector<std::pair<void *, size_t>> *evict) {
+        while (held_ + need > budget && !free_.empty()) {
+            auto it = std::prev(free_.end());
+            evict->push_back({it->second, it->first});
+            held_ -= it->first;
+            pooled_ -= it->first;
+            sizes_.erase(it->second);
+            free_.erase(it);
+        }
+        if (held_ + need > budget) return false;
+        held_ += need;
+        return true;
+    }
+    void adopt(void *p, size_t cls) { sizes_[p] = cls; }      // a block allocated by the caller
+    void unreserve(size_t cls) { held_ -= cls; }              // an allocation that failed
     void put(void *p) {
         if (!p) return;
-        free_.emplace(sizes_[p], p);
+        const size_t cls = sizes_[p];
+        free_.emplace(cls, p);
+        pooled_ += cls;
     }
     size_t held() const { return held_; }
-    size_t cached() const {
-        size_t s = 0;
-        for (auto &kv : free_) s += kv.first;
-        return s;
-    }
-    void trim_all() {
-        if (free_.empty()) return;
-        hipDeviceSynchronize();
-        for (auto &kv : free_) {
-            hipFree(kv.second);
-            held_ -= kv.first;
-            sizes_.erase(kv.second);
-        }
-        free_.clear();
-    }
-    ~BlockCache() {
+    size_t pooled() const { return pooled_; }
+    void release_all() {
         for (auto &kv : sizes_) hipFree(kv.first);
+        sizes_.clear();
+        free_.clear();
+        held_ = pooled_ = 0;
     }
 
    private:
     std::multimap<size_t, void *> free_;
     std::unordered_map<void *, size_t> sizes_;
-    size_t held_ = 0;
+    size_t held_ = 0, pooled_ = 0;
 };
 
 }  // namespace
@@ -120,16 +135,19 @@ struct fdm_server {
     bool stop = false;
     int idle = 0;
     std::deque<uint64_t> ready;       // admitted ids waiting for an executor
-    BlockCache cache;                 // guarded by mu
+    BlockPool pool;                   // guarded by mu
     std::vector<std::thread> workers;
     std::thread admitter;
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 };
 
+// Device bytes a request holds while it runs, in block size classes: Hp,
+// D and the solver workspace.
 static size_t request_footprint(int64_t n, double kT, int prec, size_t *ws) {
     *ws = fdm_workspace_bytes(n, kT, prec);
-    return *ws + 2 * (size_t)n * (size_t)n * sizeof(double);
+    const size_t mat = (size_t)n * (size_t)n * sizeof(double);
+    return size_class(*ws) + 2 * size_class(mat);
 }
 
 static void admission_loop(fdm_server *s) {
@@ -150,6 +168,42 @@ static void admission_loop(fdm_server *s) {
     }
 }
 
+// Blocks of the given classes for one request: pooled ones where they
+// exist, the rest allocated after evicting pooled blocks to stay within the
+// budget.  Called with the lock held; drops it while freeing and allocating.
+static bool acquire_blocks(fdm_server *s, std::unique_lock<std::mutex> &lk, const size_t *cls,
+                           void **out, int count) {
+    size_t need = 0;
+    for (int i = 0; i < count; ++i) {
+        out[i] = s->pool.take(cls[i]);
+        if (!out[i]) need += cls[i];
+    }
+    if (need == 0) return true;
+    std::vector<std::pair<void *, size_t>> evict;
+    if (!s->pool.reserve(need, s->budget, &evict)) {
+        for (int i = 0; i < count; ++i) s->pool.put(out[i]), out[i] = nullptr;
+        return false;
+    }
+    lk.unlock();
+    for (auto &b : evict) hipFree(b.first);
+    bool ok = true;
+    size_t failed = 0;
+    for (int i = 0; i < count; ++i) {
+        if (out[i]) continue;
+        if (hipMalloc(&out[i], cls[i]) != hipSuccess) {
+            (void)hipGetLastError();
+            out[i] = nullptr;
+            failed += cls[i];
+            ok = false;
+        }
+    }
+    lk.lock();
+    for (int i = 0; i < count; ++i)
+        if (out[i]) s->pool.adopt(out[i], cls[i]);
+    if (failed) s->pool.unreserve(failed);
+    return ok;
+}
+
 static void executor_loop(fdm_server *s) {
     hipSetDevice(s->device);
     hipStream_t stream = nullptr;
@@ -166,12 +220,14 @@ static void executor_loop(fdm_server *s) {
         Request *r = s->reqs[id].get();
         r->t_start = s->now();
         const size_t mat = (size_t)r->n * (size_t)r->n * sizeof(double);
-        double *hp = (double *)s->cache.get(mat);
-        double *d = (double *)s->cache.get(mat);
-        void *ws = s->cache.get(r->ws_bytes);
+        const size_t cls[3] = {size_class(mat), size_class(mat), size_class(r->ws_bytes)};
+        void *blk[3] = {nullptr, nullptr, nullptr};
+        const bool got = acquire_blocks(s, lk, cls, blk, 3);
+        double *hp = (double *)blk[0], *d = (double *)blk[1];
+        void *ws = blk[2];
         lk.unlock();
         int rc = FDM_OK;
-        if (!hp || !d || !ws) {
+        if (!got) {
             rc = FDM_ENOMEM;
         } else {
             hipError_t e = hipMemcpyAsync(hp, r->hp.data(), mat, hipMemcpyHostToDevice, stream);
@@ -182,25 +238,25 @@ static void executor_loop(fdm_server *s) {
             fdm_options_default(&opt);
             opt.precision = r->precision;
             opt.workspace = ws;
-            opt.workspace_bytes = r->ws_bytes;
+            opt.workspace_bytes = cls[2];
             rc = fermi_dm_solve(hp, r->n, r->n, r->n_occ, r->kT, r->tol, d, r->n, &r->e_band,
                                 &opt, &r->stats, stream);
         }
         hipStreamSynchronize(stream);
         lk.lock();
         std::vector<double>().swap(r->hp);
-        s->cache.put(hp);
-        s->cache.put(ws);
+        s->pool.put(hp);
+        s->pool.put(ws);
         if (rc != FDM_OK && rc != FDM_ENOCONV) {
-            s->cache.put(d);
+            s->pool.put(d);
             d = nullptr;
         }
         r->d_dev = d;
         r->status = rc;
         r->t_finish = s->now();
         // Hp and the workspace are released now; D stays until fdm_result
-        s->reserved -= r->footprint - (d ? mat : 0);
-        r->footprint = d ? mat : 0;
+        s->reserved -= r->footprint - (d ? cls[1] : 0);
+        r->footprint = d ? cls[1] : 0;
         s->idle += 1;
         s->cv.notify_all();
     }
@@ -283,19 +339,26 @@ int fdm_result(fdm_server *s, uint64_t ticket, double *D_out, int32_t out_on_hos
     if (!s) return FDM_EINVAL;
     std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->reqs.find(ticket);
-    if (it == s->reqs.end()) return FDM_EINVAL;
+    if (it == s->reqs.end() || it->second->collecting) return FDM_EINVAL;
     Request *r = it->second.get();
     while (r->status == 1) s->cv.wait(lk);
     if (D_out && ldd < r->n) return FDM_EINVAL;
+    // copy D out without the lock: the other requests keep running and
+    // being admitted meanwhile
+    r->collecting = true;
+    const int64_t n = r->n;
+    double *d_dev = r->d_dev;
+    lk.unlock();
     int rc = r->status;
-    const double t_result = s->now();
-    if (r->d_dev && D_out) {
-        const size_t row = (size_t)r->n * sizeof(double);
-        hipError_t e = hipMemcpy2D(D_out, (size_t)ldd * sizeof(double), r->d_dev, row, row,
-                                   (size_t)r->n,
+    if (d_dev && D_out) {
+        const size_t row = (size_t)n * sizeof(double);
+        hipError_t e = hipMemcpy2D(D_out, (size_t)ldd * sizeof(double), d_dev, row, row,
+                                   (size_t)n,
                                    out_on_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice);
         if (e != hipSuccess) rc = FDM_EHIP;
     }
+    const double t_result = s->now();
+    lk.lock();
     if (E_band) *E_band = r->e_band;
     if (stats) *stats = r->stats;
     if (times) {
@@ -304,26 +367,42 @@ int fdm_result(fdm_server *s, uint64_t ticket, double *D_out, int32_t out_on_hos
         times[2] = r->t_finish;
         times[3] = t_result;
     }
-    if (r->d_dev) s->cache.put(r->d_dev);
+    if (d_dev) s->pool.put(d_dev);
     s->reserved -= r->footprint;
-    s->reqs.erase(it);
+    s->reqs.erase(ticket);
     s->cv.notify_all();
     return rc;
+}
+
+int fdm_server_memory(fdm_server *s, size_t *held, size_t *reserved, size_t *pooled) {
+    if (!s) return FDM_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (held) *held = s->pool.held();
+    if (reserved) *reserved = s->reserved;
+    if (pooled) *pooled = s->pool.pooled();
+    return FDM_OK;
 }
 
 void fdm_server_destroy(fdm_server *s) {
     if (!s) return;
     {
-        std::unique_lock<std::mutex> lk(s->mu);
-        // let queued and running requests finish
-        while (!s->queue.empty() || !s->ready.empty() || s->idle < s->max_active) s->cv.wait(lk);
+        std::lock_guard<std::mutex> lk(s->mu);
+        // Requests that never started are dropped (queued ones hold nothing;
+        // admitted ones give back their reservation); running ones finish.
         s->stop = true;
+        for (uint64_t id : s->queue) s->reqs.erase(id);
+        for (uint64_t id : s->ready) {
+            s->reserved -= s->reqs[id]->footprint;
+            s->reqs.erase(id);
+        }
+        s->queue.clear();
+        s->ready.clear();
         s->cv.notify_all();
     }
     for (auto &t : s->workers) t.join();
     s->admitter.join();
-    for (auto &kv : s->reqs)
-        if (kv.second->d_dev) s->cache.put(kv.second->d_dev);
+    // results nobody collected, and every pooled block
+    s->pool.release_all();
     delete s;
 }
 

@@ -42,17 +42,16 @@ int hip_fail(hipError_t e, const char *what) {
 // ---------------------------------------------------------------------------
 // tile lists
 // ---------------------------------------------------------------------------
-// Upper-triangular tiles (ti <= tj) in bands of kBand tile rows, each band
+// Upper-triangular tiles (ti <= tj) in bands of kTileBand tile rows, each band
 // walked column by column: the blocks that run at the same time on one XCD
 // (a contiguous run of this list) share a few row panels of A and B, so the
 // panel k-slices they stream are reused from that XCD's L2.
-constexpr int kBand = 8;
 static std::vector<uint32_t> upper_tiles(int nt) {
     std::vector<uint32_t> v;
     v.reserve((size_t)nt * (nt + 1) / 2);
-    for (int i0 = 0; i0 < nt; i0 += kBand)
+    for (int i0 = 0; i0 < nt; i0 += kTileBand)
         for (int j = i0; j < nt; ++j)
-            for (int i = i0; i < std::min(i0 + kBand, j + 1); ++i)
+            for (int i = i0; i < std::min(i0 + kTileBand, j + 1); ++i)
                 v.push_back(((uint32_t)i << 16) | (uint32_t)j);
     return v;
 }
@@ -217,8 +216,10 @@ Resources *thread_resources(int dev) {
 // ---------------------------------------------------------------------------
 // context helpers
 // ---------------------------------------------------------------------------
-int Ctx::tile_for(int prec) const {
-    if (opt.tile == 64 || opt.tile == 128) return opt.tile;
+int Ctx::tile_for(int prec) const { return choose_tile(n, prec, opt.tile); }
+
+int choose_tile(int64_t n, int prec, int forced) {
+    if (forced == 64 || forced == 128) return forced;
     // Measured on MI355X.
     // FP32: 128-wide tiles (two waves per SIMD) once there are at least 16
     // waves of them for the chip (N >= ~11500): 108 -> 128 TFLOP/s on a
@@ -369,16 +370,19 @@ static int progress_every() {
 
 int Ctx::run_loop(int max_steps, const std::function<int(int)> &enqueue) {
     const int every = progress_every();
+    volatile const int32_t *done = &r->hm_host->done;
     int rc = enqueue(0);
     if (rc) return rc;
     hipError_t e = hipEventRecord(r->ev[0], s);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    int last = 0;  // the last step whose event was recorded
     for (int k = 1; k <= max_steps + 1; ++k) {
         if (k < max_steps) {
             rc = enqueue(k);
             if (rc) return rc;
             e = hipEventRecord(r->ev[k & 1], s);
             if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+            last = k;
         }
         e = hipEventSynchronize(r->ev[(k - 1) & 1]);
         if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
@@ -386,12 +390,22 @@ int Ctx::run_loop(int max_steps, const std::function<int(int)> &enqueue) {
             fprintf(stderr, "[fdm] n=%lld step %d done\n", (long long)n, k);
             fflush(stderr);
         }
-        if (r->hm_host->done) return FDM_OK;
+        if (*done) {
+            // The step enqueued after the observed one sees the device's done
+            // flag and returns at once; wait for it too, so that the mirror
+            // (written by whichever decide set done) and the buffers are final
+            // before the caller reads them.
+            if (last != k - 1) {
+                e = hipEventSynchronize(r->ev[last & 1]);
+                if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+            }
+            return FDM_OK;
+        }
         if (k >= max_steps) break;
     }
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    if (r->hm_host->done) return FDM_OK;
+    if (*done) return FDM_OK;
     set_error("internal: phase ended without a device decision");
     return FDM_EHIP;
 }
@@ -439,9 +453,11 @@ void Ctx::build_az_schedule(double l, double h, int steps) {
 // otherwise the device picks X^2 or 2X - X^2 from the traces.
 int Ctx::sp2_phase(int prec, void *b0, void *b1, int max_iter, int switch_mode, double tau,
                    int sched_off, void **result, int *iters) {
-    // the shifted polynomials can throw a state out of [0, 1] when the HOMO /
-    // LUMO bounds are wrong: the device then ends the phase (bit 3)
-    int rc = set_params(tau, max_iter, switch_mode | (sched_off >= 0 ? 8 : 0), 0);
+    // An eigenvalue of X outside [0, 1] (shifted polynomials built from
+    // wrong HOMO / LUMO bounds; with certified spectral bounds nothing else
+    // can put one there) ends the phase with FDM_ENOCONV instead of folding
+    // back into [0, 1] on the wrong side.
+    int rc = set_params(tau, max_iter, switch_mode | kGuard, 0);
     if (rc) return rc;
     void *bufs[2] = {b0, b1};
     // sel = 0: 2X - X^2 ;  sel = 1: X^2
@@ -528,6 +544,10 @@ int Ctx::finish(const double *Hp, int64_t ldh, const void *dm, int dm_f32, doubl
     if (rc) return rc;
     stats.band_energy = h.sums[0];
     stats.trace = h.sums[1];
+    stats.rel_trace = h.reltr;
+    stats.idem_tail_len = std::min(h.nring, 8);
+    for (int i = 0; i < stats.idem_tail_len; ++i)
+        stats.idem_tail[i] = h.idem_ring[(h.nring - stats.idem_tail_len + i) & 7];
     const int sp2_steps = stats.iters_fp64 + stats.iters_fp64_first + stats.iters_low;
     for (int k = 0; k < 4; ++k) {
         stats.branch_bits[k] = h.bits[k];
@@ -679,6 +699,116 @@ int Ctx::refine_bounds(const double *Hp, int64_t ldh, DevState *h) {
     return e == hipSuccess ? FDM_OK : hip_fail(e, "set_bounds launch");
 }
 
+// Certified spectral bounds (Sec. II.C needs bounds that hold).  The
+// Lanczos interval c -+ r of refine_bounds comes from a Krylov space, which
+// cannot see an eigenvector orthogonal to its start vector.  Every direction
+// enters the Frobenius norm, so with A = (Hp - c I) / r and M_k = A^(2^k),
+//     max_i |lambda_i(A)|^(2^(k+1)) <= ||M_k||_F^2 = sum_i lambda_i(A)^(2^(k+1)).
+// Five squarings (FP16x3 products of the library's kernel, M_k symmetric by
+// construction) and the rounding of each bounded: the stored product is
+// M_{k-1}^2 + E_k with ||E_k||_2 <= ||E_k||_F <= d_k, so by Weyl's theorem
+// rho(M_{k-1})^2 <= rho(M_k) + d_k, and from rho(M_5) <= ||M_5||_F a bound
+// b >= rho(A) follows backwards.  The bounds used are c -+ b r (clipped to
+// the Gershgorin interval): an eigenvalue the Lanczos run missed widens the
+// interval instead of breaking the expansion.  d_k covers the hi/lo
+// representation (relative 2^-22 per operand entry, plus 2^-37 absolute in
+// the FP16 subnormal range), the FP32 accumulation (24 MFMA roundings per
+// 256-deep partial sum, one per fold, and the final stores) and the
+// FP32 rounding of A, each doubled.  A power that overflows FP16 (|entries|
+// >= 16, i.e. rho(A) far above 1) gives non-finite sums: the Gershgorin
+// interval is used then.
+int Ctx::certify_bounds(const double *Hp, int64_t ldh, DevState *h) {
+    const double glo = stats.gersh_min, ghi = stats.gersh_max;
+    const double c = 0.5 * (h->emin + h->emax), rad = 0.5 * (h->emax - h->emin);
+    stats.lanczos_min = h->emin;
+    stats.lanczos_max = h->emax;
+    if (!(rad > 0.0) || (h->emin <= glo && h->emax >= ghi)) return FDM_OK;
+    const size_t m = (size_t)r->lay.np * r->lay.ld;
+    // two (FP32 matrix, hi/lo companions) slots, carved from the FP64
+    // working matrices 1 and 2 (8 bytes per element each), free before X_0
+    float *mat[2];
+    uint16_t *hl[2];
+    for (int i = 0; i < 2; ++i) {
+        char *b = (char *)(r->x64 + (size_t)(i + 1) * m);
+        mat[i] = (float *)b;
+        hl[i] = (uint16_t *)(b + m * sizeof(float));
+    }
+    int rc = set_params(0.0, 1, 0, 1);  // clears the certificate slots
+    if (rc) return rc;
+    int np = 0;
+    hipError_t e = launch_affine(0, Hp, ldh, 1, mat[0], r->lay.ld, (int)n, (int)r->lay.np,
+                                 1.0 / rad, -c / rad, 0, r->st, r->part, &np, s);
+    if (e != hipSuccess) return hip_fail(e, "affine launch");
+    e = launch_split(P_F16X3, mat[0], hl[0], r->lay.ld, r->lay.np, s);
+    if (e != hipSuccess) return hip_fail(e, "split launch");
+    rc = decide(D_CERT, np, 4);
+    if (rc) return rc;
+    constexpr int kSq = 5;
+    const int bt = tile_for(P_F16X3);
+    for (int k = 1; k <= kSq; ++k) {
+        ProdArgs a;
+        memset(&a, 0, sizeof(a));
+        const int src = (k - 1) & 1, dst = k & 1;
+        a.A = a.B = mat[src];
+        a.C = mat[dst];
+        a.Ahl = a.Bhl = hl[src];
+        a.Chl = hl[dst];
+        a.ld = r->lay.ld;
+        a.n = (int32_t)n;
+        a.kext = (int32_t)round_up(n, kKStep);
+        a.tiles = (bt == 128) ? r->tiles128 : r->tiles64;
+        a.ntiles = (bt == 128) ? r->lay.ntiles128 : r->lay.ntiles64;
+        a.coef[0][0] = a.coef[1][0] = 1.0;
+        a.partials = r->part;
+        e = launch_symprod(P_F16X3, bt, a, s);
+        if (e != hipSuccess) return hip_fail(e, "symmetric product launch");
+        rc = decide(D_CERT, a.ntiles, 4);
+        if (rc) return rc;
+    }
+    DevState hs;
+    rc = read_state(&hs);
+    if (rc) return rc;
+    const double nn = (double)n, K = (double)round_up(n, kKStep);
+    const double cu = 2.0 * (3.0 * ldexp(1.0, -22) + (27.0 + K / 256.0) * ldexp(1.0, -24));
+    double F[kSq + 1];
+    bool finite = hs.ncert == kSq + 1;
+    for (int k = 0; k <= kSq && finite; ++k) {
+        F[k] = sqrt(hs.cert[k]);
+        finite = std::isfinite(F[k]);
+    }
+    double b = INFINITY;
+    if (finite) {
+        b = F[kSq] * (1.0 + 1e-12);
+        for (int k = kSq; k >= 1; --k) {
+            const double d = cu * F[k - 1] * F[k - 1] + 6e-11 * nn * F[k - 1] + 1e-20 * nn * nn;
+            b = sqrt(b + d);
+        }
+        b += 2.0 * ldexp(1.0, -24) * F[0] + 1e-14;  // FP32 rounding of A
+    }
+    stats.cert_radius = b;
+    double lo = glo, hi = ghi;
+    if (std::isfinite(b)) {
+        lo = std::max(glo, c - b * rad);
+        hi = std::min(ghi, c + b * rad);
+        stats.bounds_certified = 1;
+    } else {
+        stats.bounds_certified = -1;
+    }
+    h->emin = lo;
+    h->emax = hi;
+    stats.e_min = lo;
+    stats.e_max = hi;
+    e = launch_set_bounds(r->st, lo, hi, s);
+    return e == hipSuccess ? FDM_OK : hip_fail(e, "set_bounds launch");
+}
+
+int Ctx::tight_bounds(const double *Hp, int64_t ldh, DevState *h) {
+    int rc = refine_bounds(Hp, ldh, h);
+    if (rc) return rc;
+    if (stats.lanczos_steps == 0) return FDM_OK;  // Gershgorin kept
+    return certify_bounds(Hp, ldh, h);
+}
+
 // k Lanczos steps on the projection of Hp - sigma I onto the occupied
 // (unocc = 0) or unoccupied (unocc = 1) subspace of the density matrix D.
 // Returns the extreme Ritz value (largest for the occupied side, smallest
@@ -807,7 +937,7 @@ int Ctx::solve_zero_t_once(const double *Hp, int64_t ldh, double *D, int64_t ldd
         return FDM_ENOCONV;
     }
     if (opt.bounds == 1) {
-        rc = refine_bounds(Hp, ldh, &h);
+        rc = tight_bounds(Hp, ldh, &h);
         if (rc) return rc;
     }
     const int prec = opt.precision;
@@ -827,11 +957,50 @@ int Ctx::solve_zero_t_once(const double *Hp, int64_t ldh, double *D, int64_t ldd
     const int sched = stats.accelerated == 1 ? 0 : -1;
     rc = set_params(0.0, max_iter, 0, 1);
     if (rc) return rc;
+    phase_done(0);
     int np = 0;
     double *x64 = r->x64;
     const size_t m64 = (size_t)r->lay.np * r->lay.ld;
     double *X64[3] = {x64, x64 + m64, x64 + 2 * m64};
     float *X32[2] = {r->x32, r->x32 + m64};
+
+    if (opt.reltr_schedule) {
+        // The paper's schedule (Sec. III.A, Sec. IV): SP2 products in the
+        // working precision until the relative trace change drops below
+        // reltr_switch, then FP64 products until it drops below reltr_stop;
+        // the last iterate is D.  RelTr_n = Tr(X_n - X_n^2) / Tr X_n here,
+        // since both SP2 branches change the trace by Tr(X - X^2).
+        stats.reltr_schedule = 1;
+        void *res = nullptr;
+        int it = 0;
+        if (prec != P_F64) {
+            split_prec = prec;
+            rc = affine(0, Hp, ldh, 1, X32[0], 0, 0, 1, &np);
+            if (rc) return rc;
+            rc = decide(D_INIT, np, 4);
+            if (rc) return rc;
+            rc = sp2_phase(prec, X32[0], X32[1], max_iter, 1 | kRelTrStop, opt.reltr_switch, -1,
+                           &res, &it);
+            if (rc) return rc;
+            stats.iters_low = it;
+            phase_done(2);
+            if (status) {
+                stats.idempotency = r->hm_host->idem;
+                return finish(Hp, ldh, res, 1, D, ldd, E_band);
+            }
+            rc = affine(1, res, r->lay.ld, 0, X64[0], 1.0, 0.0, 0, &np);
+        } else {
+            rc = affine(0, Hp, ldh, 0, X64[0], 0, 0, 1, &np);
+        }
+        if (rc) return rc;
+        rc = decide(D_INIT, np, 4);
+        if (rc) return rc;
+        rc = sp2_phase(P_F64, X64[0], X64[1], max_iter, kRelTrStop, opt.reltr_stop, -1, &res, &it);
+        if (rc) return rc;
+        stats.iters_fp64 = it;
+        stats.idempotency = r->hm_host->idem;  // of the iterate before the returned one
+        return finish(Hp, ldh, res, 0, D, ldd, E_band);
+    }
 
     if (prec == P_F64) {
         rc = affine(0, Hp, ldh, 0, X64[0], 0, 0, 1, &np);
@@ -842,6 +1011,7 @@ int Ctx::solve_zero_t_once(const double *Hp, int64_t ldh, double *D, int64_t ldd
         int it = 0;
         rc = sp2_phase(P_F64, X64[0], X64[1], max_iter, 0, 0.0, sched, &res, &it);
         if (rc) return rc;
+        phase_done(1);
         stats.iters_fp64 = it;
         stats.idempotency = r->hm_host->idem;
         return finish(Hp, ldh, res, 0, D, ldd, E_band);
@@ -900,6 +1070,7 @@ int Ctx::solve_zero_t_once(const double *Hp, int64_t ldh, double *D, int64_t ldd
         int it = 0;
         rc = sp2_phase(P_F64, X64[0], X64[1], k64, 2, tau, sched, &res, &it);
         if (rc) return rc;
+        phase_done(1);
         stats.iters_fp64_first = it;
         if (r->hm_host->done && r->hm_host->result_iter < k64 && r->hm_host->idem <= tol) {
             stats.idempotency = r->hm_host->idem;
@@ -921,6 +1092,7 @@ int Ctx::solve_zero_t_once(const double *Hp, int64_t ldh, double *D, int64_t ldd
     rc = sp2_phase(prec, X32[0], X32[1], max_iter, 1, tau,
                    sched < 0 ? -1 : stats.iters_fp64_first, &cur32, &itl);
     if (rc) return rc;
+    phase_done(2);
     stats.iters_low = itl;
     if (status) {  // the iterate left [0, 1]: report it
         stats.idempotency = r->hm_host->idem;
@@ -940,6 +1112,12 @@ int Ctx::solve_zero_t_once(const double *Hp, int64_t ldh, double *D, int64_t ldd
     if (rc) return rc;
     stats.mcweeny_steps = steps;
     return finish(Hp, ldh, res64, 0, D, ldd, E_band);
+}
+
+void Ctx::phase_done(int i) {
+    const auto now = std::chrono::steady_clock::now();
+    stats.phase_ms[i] += std::chrono::duration<double, std::milli>(now - tmark).count();
+    tmark = now;
 }
 
 void Ctx::finalize_timing() {
@@ -981,6 +1159,11 @@ int fdm_options_default(fdm_options *opt) {
     opt->lumo = NAN;
     opt->mu_guess = NAN;
     opt->estimate_gap = 0;
+    opt->reltr_schedule = 0;
+    opt->reltr_switch = 5e-4;
+    opt->reltr_stop = 5e-8;
+    opt->trfoe = 0;
+    opt->trfoe_depth = 0;
     return FDM_OK;
 }
 
@@ -1017,7 +1200,8 @@ int fermi_dm_solve(const double *Hp, int64_t N, int64_t ldh, double n_occ, doubl
     if (!Hp || !D || N <= 0 || N >= 65535 * 64 || ldh < N || ldd < N || !(tol > 0.0) ||
         !(kT >= 0.0) || !std::isfinite(kT) || opt.precision < 0 || opt.precision >= FDM_NPREC ||
         opt.max_iter <= 0 || (opt.tile != 0 && opt.tile != 64 && opt.tile != 128) ||
-        opt.bounds < 0 || opt.bounds > 1) {
+        opt.bounds < 0 || opt.bounds > 1 || opt.trfoe_depth < 0 ||
+        (opt.reltr_schedule && !(opt.reltr_switch > 0.0 && opt.reltr_stop > 0.0))) {
         set_error("invalid argument");
         return FDM_EINVAL;
     }
@@ -1049,6 +1233,8 @@ int fermi_dm_solve(const double *Hp, int64_t N, int64_t ldh, double n_occ, doubl
     c.kT = kT;
     memset(&c.stats, 0, sizeof(c.stats));
     c.stats.homo_ub = c.stats.lumo_lb = NAN;
+    c.stats.lanczos_min = c.stats.lanczos_max = c.stats.cert_radius = NAN;
+    c.tmark = t0;
     const Layout L = plan_layout(N, kT > 0.0, opt.precision);
     int rc = r->bind(L, opt.workspace, opt.workspace_bytes, c.s);
     if (rc == FDM_OK && opt.validate) rc = c.validate_symmetric(Hp, ldh);
@@ -1059,6 +1245,7 @@ int fermi_dm_solve(const double *Hp, int64_t N, int64_t ldh, double n_occ, doubl
         hipError_t e2 = hipStreamSynchronize(c.s);
         if (e2 != hipSuccess) rc = hip_fail(e2, "hipStreamSynchronize");
         c.finalize_timing();
+        c.phase_done(3);
     }
     c.stats.status = rc;
     c.stats.tile = c.used_tile;
@@ -1153,6 +1340,11 @@ int fdm_sym_product(int32_t precision, const double *A, const double *B, const d
         sums[0] = h.sums[0];
         sums[1] = h.sums[1];
         sums[2] = h.sums[2];
+    }
+    if (!std::isfinite(h.sums[0]) || !std::isfinite(h.sums[1]) || !std::isfinite(h.sums[2])) {
+        set_error("non-finite product (inputs non-finite, or |entries| >= 65504/4096 in an "
+                  "FP16 form)");
+        return FDM_ENONFINITE;
     }
     return FDM_OK;
 }

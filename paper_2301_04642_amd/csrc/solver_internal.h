@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <chrono>
 #include <functional>
 #include <vector>
 
@@ -89,6 +90,7 @@ struct Ctx {
     std::vector<uint8_t> az_branch;
     std::vector<double> az_gap;  // h - l before the first and after each accelerated step
     std::vector<Timed> timed;
+    std::chrono::steady_clock::time_point tmark = std::chrono::steady_clock::now();
 
     int tile_for(int prec) const;
     int product(int prec, const void *A, const void *B, const void *E, void *C, const double c0[3],
@@ -107,6 +109,8 @@ struct Ctx {
     int read_state(DevState *out);
     int bounds(const double *Hp, int64_t ldh, DevState *h);
     int refine_bounds(const double *Hp, int64_t ldh, DevState *h);
+    int certify_bounds(const double *Hp, int64_t ldh, DevState *h);
+    int tight_bounds(const double *Hp, int64_t ldh, DevState *h);
     int estimate_gap(const double *Hp, int64_t ldh, const double *D, int64_t ldd);
     int projected_ritz(const double *Hp, int64_t ldh, const double *D, int64_t ldd, int unocc,
                        double sigma, int k, double *theta, double *resid);
@@ -121,6 +125,8 @@ struct Ctx {
     int fermi_operator(const double *Hp, int64_t ldh, double mu, int depth, int prec,
                        void **result, int *result_f32, double *trace, double *trace_dd);
     void finalize_timing();
+    void phase_done(int i);  // adds the host time since the last mark to stats.phase_ms[i]
+    int solve_trfoe(const double *Hp, int64_t ldh, double *D, int64_t ldd, double *E_band);
 };
 
 }  // namespace fdm

@@ -9,7 +9,7 @@ import numpy as np
 
 from oracle import density as den
 from oracle import azrfoe as az
-from oracle import fd, sp2
+from oracle import fd, sp2, trfoe
 from oracle.eig import jacobi_eigh
 import workloads
 
@@ -398,6 +398,81 @@ def check_lapack_eigh(eigh=den.eigh_lapack, n=64):
     assert np.abs((v * w) @ v.T - wl.hp).max() < 1e-13
 
 
+def check_sp2_reltr_stop(sp2fn=sp2.sp2):
+    """The relative-trace stop (Sec. III.A): on a diagonal H the dense
+    iteration follows the scalar maps, and the returned iterate is the first
+    whose trace changed by at most the threshold; both SP2 branches change
+    the trace by Tr(X - X^2), so RelTr of X_{n+1} is (t - s)/t at X_n."""
+    rng = np.random.default_rng(31)
+    rng.uniform(size=40)
+    n, k = 120, 90
+    lam = np.sort(np.concatenate([rng.uniform(-1, -0.2, k), rng.uniform(0.1, 1, n - k)]))
+    for thr in (5e-3, 5e-4, 5e-8):
+        x, info = sp2fn(np.diag(lam), k, reltr_stop=thr, bounds=(lam[0], lam[-1]))
+        s = (lam[-1] - lam) / (lam[-1] - lam[0])
+        for it in range(1, 200):
+            t, q = s.sum(), (s * s).sum()
+            s = s * s if abs(q - k) <= abs(2 * t - q - k) else 2 * s - s * s
+            if (t - q) / t <= thr:
+                break
+        assert info["iterations"] == it, (info["iterations"], it)
+        assert np.allclose(np.diag(x), s, atol=1e-15, rtol=0)
+
+
+def check_reltr_paper_count(count=az.scalar_iterations):
+    """Sec. IV: stopped at RelTr 5e-8, the plain expansion takes about 50
+    products on the paper's matrix (here its exact N = 8192 spectrum, 90%
+    occupied, bounds at the extreme eigenvalues)."""
+    n = 8192
+    lam = den.banded_eigenvalues(workloads.paper_e1_matrix(n), 80)
+    c = count(lam, int(0.9 * n), 1e-8, lam[0], lam[-1], reltr_stop=5e-8)
+    assert 45 <= c <= 55, c
+
+
+def check_trfoe_dense_vs_spectral(dense=trfoe.dense, scal=trfoe.scalar, n=64):
+    """The truncated expansion is a matrix function: the dense iteration on
+    Hp = Q diag(lam) Q^T equals Q diag(G_m(lam)) Q^T, with the same
+    trace-chosen branches, at 85% and 25% filling."""
+    wl = workloads.standard_workload("uniform", n=n)
+    bounds = sp2.gershgorin_bounds(wl.hp)
+    for frac in (0.85, 0.25):
+        nocc = frac * n
+        x, info = dense(wl.hp, nocc, 0.0016, bounds=bounds)
+        g, sinfo = scal(wl.lam, nocc, 0.0016, *bounds)
+        assert info["branches"] == sinfo["branches"]
+        assert np.abs(x - (wl.q * g) @ wl.q.T).max() < 1e-12
+
+
+def check_trfoe_properties(scal=trfoe.scalar):
+    """Occupations lie in [0, 1] and fall with the energy (both maps are
+    increasing on [0, 1]); with a gap and many steps the truncated expansion
+    becomes the zero-temperature projector (Z-RFOE); the depth grows as the
+    temperature falls."""
+    lam = np.linspace(-1, 1, 301)
+    g, info = scal(lam, 120.3, 0.0016, -1.0, 1.0)
+    assert g.min() >= 0.0 and g.max() <= 1.0
+    assert np.all(np.diff(g) <= 1e-15)
+    lam2 = np.concatenate([np.linspace(-1, -0.3, 40), np.linspace(0.2, 1, 60)])
+    g2, _ = scal(lam2, 40, 0.0016, -1.0, 1.0, m=60)
+    assert np.abs(g2 - (lam2 < 0)).max() < 1e-12
+    assert trfoe.depth(0.0016, -1, 1) > trfoe.depth(0.01, -1, 1) > trfoe.depth(0.05, -1, 1)
+
+
+def check_trfoe_slope(scal=trfoe.scalar):
+    """The depth rule's intent: the smeared step's slope at its half-way
+    point is within a factor 2 of the Fermi function's beta/4 (measured on a
+    fine uniform spectrum at 30%, 50% and 85% filling, kT = 0.0016 and
+    0.01 Ha)."""
+    lam = np.linspace(-1, 1, 4001)
+    for frac in (0.3, 0.5, 0.85):
+        for kT in (0.0016, 0.01):
+            g, _ = scal(lam, frac * lam.size, kT, -1.0, 1.0)
+            i = int(np.argmin(np.abs(g - 0.5)))
+            slope = -(g[i + 1] - g[i - 1]) / (lam[i + 1] - lam[i - 1])
+            ratio = slope / (0.25 / kT)
+            assert 0.5 <= ratio <= 2.0, (frac, kT, ratio)
+
+
 ALL_PINS = [
     check_jacobi_2x2, check_jacobi_toeplitz, check_jacobi_known_spectrum, check_jacobi_vs_lapack,
     check_density_invariants, check_density_vs_construction, check_shift_scale_and_permutation,
@@ -406,5 +481,7 @@ ALL_PINS = [
     check_fd_recursion_closed_form, check_fd_recursion_dense, check_banded_eigenvalues,
     check_azrfoe_fold, check_azrfoe_diagonal, check_azrfoe_matches_definition,
     check_azrfoe_paper_counts, check_sp2_stop_rule, check_density_rows, check_kron_workload,
-    check_paper_e1_band, check_eps_metrics, check_lapack_eigh,
+    check_paper_e1_band, check_eps_metrics, check_lapack_eigh, check_sp2_reltr_stop,
+    check_reltr_paper_count, check_trfoe_dense_vs_spectral, check_trfoe_properties,
+    check_trfoe_slope,
 ]

@@ -262,3 +262,44 @@ def test_mutant_eps1_unnormalised():
 
 def test_mutant_eps2_unsigned():
     assert _fails(pins.check_eps_metrics, e2=lambda e, r: abs((e - r) / r))
+
+
+def test_mutant_reltr_absolute_change():
+    def bad(h, n_occ, tol=1e-10, max_iter=100, bounds=None, reltr_stop=None):
+        x = sp2.initial_iterate(h, *bounds)
+        for it in range(1, max_iter):
+            t, s = np.trace(x), np.sum(x * x)
+            p = x @ x
+            x = p if sp2.choose_square(t, s, n_occ) else 2 * x - p
+            if abs(np.trace(x) - t) <= reltr_stop:          # not relative
+                break
+        return x, dict(iterations=it)
+    assert _fails(pins.check_sp2_reltr_stop, sp2fn=bad)
+
+
+def test_mutant_trfoe_wrong_map():
+    from oracle import trfoe
+
+    def bad(lam, n_occ, kT, e_min, e_max, m=None):
+        m = trfoe.depth(kT, e_min, e_max) if m is None else m
+        x = (e_max - np.asarray(lam)) / (e_max - e_min)
+        for _ in range(m):
+            t, s = x.sum(), (x * x).sum()
+            x = x * x if sp2.choose_square(t, s, n_occ) else 2 * x + x * x   # sign
+        return x, dict(branches=[], depth=m)
+    assert _fails(pins.check_trfoe_properties, scal=bad)
+
+
+def test_mutant_trfoe_depth_base_two(monkeypatch):
+    from oracle import trfoe
+    monkeypatch.setattr(trfoe, "GROWTH", 2.0)
+    assert _fails(pins.check_trfoe_slope, scal=trfoe.scalar)
+
+
+def test_mutant_trfoe_dense_transposed_start():
+    from oracle import trfoe
+
+    def bad(h, n_occ, kT, bounds=None, m=None):
+        e_min, e_max = bounds
+        return trfoe.dense(h - 0.05 * np.eye(h.shape[0]), n_occ, kT, bounds=(e_min, e_max), m=m)
+    assert _fails(pins.check_trfoe_dense_vs_spectral, dense=bad)

@@ -265,6 +265,22 @@ int fdm_sym_product(int32_t precision, const double *A, const double *B, const d
                     double gamma, double *sums, int32_t tile, void *stream);
 
 /*
+ * fdm_sym_product_noalloc -- fdm_sym_product for callers that cannot
+ * allocate device memory (code under stream capture, serving loops that
+ * forbid hipMalloc).  Same arguments, kernels, results and errors as
+ * fdm_sym_product; it allocates no device or pinned host memory.  Its
+ * workspace is a fixed 64 MiB device array inside the library (one per GPU,
+ * held until the process ends), which limits N to 1408: larger N returns
+ * FDM_EINVAL with a message.  Every call on one GPU uses that GPU's array and
+ * overwrites the previous call's contents (the call clears what must start at
+ * zero), so calls that overlap on one GPU -- two streams or two host threads
+ * at once -- race and must be serialised by the caller.
+ */
+int fdm_sym_product_noalloc(int32_t precision, const double *A, const double *B, const double *E,
+                            double *C, int64_t N, int64_t ld, double alpha, double beta,
+                            double gamma, double *sums, int32_t tile, void *stream);
+
+/*
  * fdm_band_energy -- Tr(H D) = sum_ij H_ij D_ij and Tr D in FP64 (the band
  * energy of Sec. III.C).
  *  H, D  device, N x N, leading dimensions ldh, ldd.   out host double[2].

@@ -27,7 +27,7 @@ PREC_NAMES = {v: k for k, v in PRECISIONS.items()}
 EXPORTS = ("fdm_options_default", "fdm_workspace_bytes", "fermi_dm_solve", "fdm_strerror",
            "fdm_last_error", "fdm_gershgorin", "fdm_sym_product", "fdm_band_energy",
            "fdm_fermi_operator", "fdm_server_create", "fdm_submit", "fdm_poll", "fdm_result",
-           "fdm_server_memory", "fdm_server_destroy")
+           "fdm_server_memory", "fdm_server_destroy", "fdm_sym_product_noalloc")
 
 
 class fdm_options(ctypes.Structure):
@@ -112,6 +112,8 @@ def _load():
                                           VP]),
         "fdm_sym_product": (ctypes.c_int, [I32, P, P, P, P, I64, I64, D, D, D, ctypes.POINTER(D),
                                            I32, VP]),
+        "fdm_sym_product_noalloc": (ctypes.c_int, [I32, P, P, P, P, I64, I64, D, D, D,
+                                                   ctypes.POINTER(D), I32, VP]),
         "fdm_band_energy": (ctypes.c_int, [P, I64, P, I64, I64, ctypes.POINTER(D), VP]),
         "fdm_fermi_operator": (ctypes.c_int, [P, I64, I64, D, D, I32, I32, P, I64,
                                               ctypes.POINTER(D), VP]),
@@ -245,6 +247,23 @@ def fdm_sym_product(precision, A, B, E, C, alpha=1.0, beta=0.0, gamma=0.0, tile=
     _check(_lib.fdm_sym_product(prec, _ptr(A), _ptr(B), _ptr(E), _ptr(C), n, ld, float(alpha),
                                 float(beta), float(gamma), sums, int(tile), _stream(stream)),
            "fdm_sym_product")
+    return sums[0], sums[1], sums[2]
+
+
+def fdm_sym_product_noalloc(precision, A, B, E, C, alpha=1.0, beta=0.0, gamma=0.0, tile=0,
+                            stream=None):
+    """fdm_sym_product on the library's fixed device workspace (no allocation;
+    N <= 1408).  Returns (Tr C, ||C||_F^2, ||AB - E||_F^2)."""
+    n = A.shape[0]
+    ld = _check_matrix(A, n, "A")
+    for t, nm in ((B, "B"), (C, "C")) + (((E, "E"),) if E is not None else ()):
+        if _check_matrix(t, n, nm) != ld:
+            raise ValueError("A, B, E and C must share one leading dimension")
+    sums = (ctypes.c_double * 3)()
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(_lib.fdm_sym_product_noalloc(prec, _ptr(A), _ptr(B), _ptr(E), _ptr(C), n, ld,
+                                        float(alpha), float(beta), float(gamma), sums, int(tile),
+                                        _stream(stream)), "fdm_sym_product_noalloc")
     return sums[0], sums[1], sums[2]
 
 

@@ -64,13 +64,16 @@ static int64_t ntiles_for(int64_t n, int bt) {
 // ---------------------------------------------------------------------------
 // workspace
 // ---------------------------------------------------------------------------
-Layout plan_layout(int64_t n, bool finite, int prec) {
+// Workspace of n64 FP64 and n32 FP32 working matrices (each FP32 one with
+// its hi/lo 16-bit companions), per-tile partials, tile lists, Lanczos
+// vectors and the device state, each part 256-byte aligned.
+static Layout plan_mats(int64_t n, int n64, int n32) {
     Layout L;
     L.n = n;
     L.np = round_up(std::max<int64_t>(n, 1), kPadEdge);
     L.ld = L.np;
-    L.n64 = finite ? 5 : 3;
-    L.n32 = (prec == P_F64) ? 0 : (finite ? 5 : 2);
+    L.n64 = n64;
+    L.n32 = n32;
     const size_t mat64 = (size_t)L.np * L.ld * 8, mat32 = (size_t)L.np * L.ld * 4;
     const int64_t tiles64 = ntiles_for(n, 64), tiles128 = ntiles_for(n, 128);
     const int64_t parts = std::max<int64_t>({tiles64, (L.np + 3) / 4, 1});
@@ -98,8 +101,31 @@ Layout plan_layout(int64_t n, bool finite, int prec) {
     return L;
 }
 
+Layout plan_layout(int64_t n, bool finite, int prec) {
+    return plan_mats(n, finite ? 5 : 3, (prec == P_F64) ? 0 : (finite ? 5 : 2));
+}
+
+// A single product call: four working matrices (A, B, E, C) of the
+// product's precision (FP64, or FP32 masters with companions).
+Layout plan_product_layout(int64_t n, int prec) {
+    return prec == P_F64 ? plan_mats(n, 4, 0) : plan_mats(n, 0, 4);
+}
+
+void Resources::view(const Layout &L, char *mem) {
+    lay = L;
+    x64 = (double *)(mem + L.off64);
+    x32 = (float *)(mem + L.off32);
+    x16 = (uint16_t *)(mem + L.off16);
+    part = (double *)(mem + L.off_part);
+    tiles64 = (uint32_t *)(mem + L.off_tiles64);
+    tiles128 = (uint32_t *)(mem + L.off_tiles128);
+    st = (DevState *)(mem + L.off_state);
+    lanczos = (double *)(mem + L.off_lanczos);
+}
+
 Resources::~Resources() {
-    for (hipEvent_t e : ev) hipEventDestroy(e);
+    for (hipEvent_t e : ev)
+        if (e) hipEventDestroy(e);
     for (hipEvent_t e : tev) hipEventDestroy(e);
     if (owned && base) hipFree(base);
     // the mapped host mirror is intentionally kept until process exit
@@ -161,15 +187,7 @@ int Resources::bind(const Layout &L, void *user_mem, size_t user_bytes, hipStrea
     // re-zero it and re-upload the tile lists.
     const bool fresh = user_mem != nullptr || (mem != bound_mem) ||
                        bound_key != (L.n * 16 + L.n64 * 4 + L.n32) || bound_ld != L.ld;
-    lay = L;
-    x64 = (double *)(mem + L.off64);
-    x32 = (float *)(mem + L.off32);
-    x16 = (uint16_t *)(mem + L.off16);
-    part = (double *)(mem + L.off_part);
-    tiles64 = (uint32_t *)(mem + L.off_tiles64);
-    tiles128 = (uint32_t *)(mem + L.off_tiles128);
-    st = (DevState *)(mem + L.off_state);
-    lanczos = (double *)(mem + L.off_lanczos);
+    view(L, mem);
     if (fresh) {
         // zero every matrix (the padding must hold zeros) and upload tile lists
         e = hipMemsetAsync(mem, 0, L.off_part, s);  // FP64, FP32 and 16-bit companions
@@ -1137,6 +1155,73 @@ void Ctx::finalize_timing() {
 // ===========================================================================
 using namespace fdm;
 
+namespace fdm {
+
+bool sym_product_args_ok(int32_t precision, const double *A, const double *B, const double *E,
+                         const double *C, int64_t N, int64_t ld, int32_t tile) {
+    return A && B && C && N > 0 && ld >= N && N < 65535 * 64 && precision >= 0 &&
+           precision < FDM_NPREC && (tile == 0 || tile == 64 || tile == 128) && C != A &&
+           C != B && !(E && C == E);
+}
+
+// The body of fdm_sym_product on a workspace already bound to
+// plan_product_layout(N, precision) (zero padding, tile lists in place).
+int sym_product_bound(Resources *r, int32_t precision, const double *A, const double *B,
+                      const double *E, double *C, int64_t N, int64_t ld, double alpha,
+                      double beta, double gamma, double *sums, int32_t tile, hipStream_t s) {
+    Ctx c;
+    c.r = r;
+    c.s = s;
+    fdm_options_default(&c.opt);
+    c.opt.tile = tile;
+    c.n = N;
+    const bool lo = precision != P_F64;
+    c.split_prec = precision;
+    // Operands are packed into zero-padded working matrices of the product's
+    // precision (FP64, or the FP32 master of the low-precision forms).
+    const Layout &L = r->lay;
+    const size_t m = (size_t)L.np * L.ld;
+    void *slot[4];
+    for (int i = 0; i < 4; ++i)
+        slot[i] = lo ? (void *)(r->x32 + i * m) : (void *)(r->x64 + i * m);
+    const double *src[3] = {A, B, E};
+    void *dst[3] = {slot[0], slot[1], slot[2]};
+    if (B == A) dst[1] = slot[0];
+    if (E == A) dst[2] = slot[0];
+    else if (E == B) dst[2] = dst[1];
+    int rc;
+    for (int i = 0; i < 3; ++i) {
+        if (!src[i]) continue;
+        if ((i == 1 && B == A) || (i == 2 && (E == A || E == B))) continue;
+        rc = c.affine(0, src[i], ld, lo ? 1 : 0, dst[i], 1.0, 0.0, 0, nullptr);
+        if (rc) return rc;
+    }
+    const double coef[3] = {alpha, beta, gamma};
+    rc = c.product(precision, dst[0], dst[1], E ? dst[2] : nullptr, slot[3], coef, nullptr, false,
+                   false);
+    if (rc) return rc;
+    rc = c.decide(D_SUMS, c.last_ntiles, 4);
+    if (rc) return rc;
+    hipError_t e = launch_copy_out(lo ? 1 : 0, slot[3], L.ld, C, ld, (int)N, s);
+    if (e != hipSuccess) return hip_fail(e, "copy-out launch");
+    DevState h;
+    rc = c.read_state(&h);
+    if (rc) return rc;
+    if (sums) {
+        sums[0] = h.sums[0];
+        sums[1] = h.sums[1];
+        sums[2] = h.sums[2];
+    }
+    if (!std::isfinite(h.sums[0]) || !std::isfinite(h.sums[1]) || !std::isfinite(h.sums[2])) {
+        set_error("non-finite product (inputs non-finite, or |entries| >= 65504/4096 in an "
+                  "FP16 form)");
+        return FDM_ENONFINITE;
+    }
+    return FDM_OK;
+}
+
+}  // namespace fdm
+
 extern "C" {
 
 int fdm_options_default(fdm_options *opt) {
@@ -1289,64 +1374,16 @@ int fdm_sym_product(int32_t precision, const double *A, const double *B, const d
                     double *C, int64_t N, int64_t ld, double alpha, double beta, double gamma,
                     double *sums, int32_t tile, void *stream) {
     set_error("");
-    if (!A || !B || !C || N <= 0 || ld < N || precision < 0 || precision >= FDM_NPREC ||
-        (tile != 0 && tile != 64 && tile != 128) || C == A || C == B || (E && C == E))
-        return FDM_EINVAL;
+    if (!sym_product_args_ok(precision, A, B, E, C, N, ld, tile)) return FDM_EINVAL;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     Resources *r = thread_resources(dev);
     if (!r) return FDM_EHIP;
-    Ctx c;
-    c.r = r;
-    c.s = (hipStream_t)stream;
-    fdm_options_default(&c.opt);
-    c.opt.tile = tile;
-    c.n = N;
-    const bool lo = precision != P_F64;
-    c.split_prec = precision;
-    // Operands are packed into zero-padded working matrices of the product's
-    // precision (FP64, or the FP32 master of the low-precision forms).
-    Layout L = plan_layout(N, true, lo ? P_F32 : P_F64);
-    int rc = r->bind(L, nullptr, 0, c.s);
+    int rc = r->bind(plan_product_layout(N, precision), nullptr, 0, (hipStream_t)stream);
     if (rc) return rc;
-    const size_t m = (size_t)L.np * L.ld;
-    void *slot[4];
-    for (int i = 0; i < 4; ++i)
-        slot[i] = lo ? (void *)(r->x32 + i * m) : (void *)(r->x64 + i * m);
-    const double *src[3] = {A, B, E};
-    void *dst[3] = {slot[0], slot[1], slot[2]};
-    if (B == A) dst[1] = slot[0];
-    if (E == A) dst[2] = slot[0];
-    else if (E == B) dst[2] = dst[1];
-    for (int i = 0; i < 3; ++i) {
-        if (!src[i]) continue;
-        if ((i == 1 && B == A) || (i == 2 && (E == A || E == B))) continue;
-        rc = c.affine(0, src[i], ld, lo ? 1 : 0, dst[i], 1.0, 0.0, 0, nullptr);
-        if (rc) return rc;
-    }
-    const double coef[3] = {alpha, beta, gamma};
-    rc = c.product(precision, dst[0], dst[1], E ? dst[2] : nullptr, slot[3], coef, nullptr, false,
-                   false);
-    if (rc) return rc;
-    rc = c.decide(D_SUMS, c.last_ntiles, 4);
-    if (rc) return rc;
-    e = launch_copy_out(lo ? 1 : 0, slot[3], L.ld, C, ld, (int)N, c.s);
-    if (e != hipSuccess) return hip_fail(e, "copy-out launch");
-    DevState h;
-    rc = c.read_state(&h);
-    if (rc) return rc;
-    if (sums) {
-        sums[0] = h.sums[0];
-        sums[1] = h.sums[1];
-        sums[2] = h.sums[2];
-    }
-    if (!std::isfinite(h.sums[0]) || !std::isfinite(h.sums[1]) || !std::isfinite(h.sums[2])) {
-        set_error("non-finite product (inputs non-finite, or |entries| >= 65504/4096 in an "
-                  "FP16 form)");
-        return FDM_ENONFINITE;
-    }
-    return FDM_OK;
+    return sym_product_bound(r, precision, A, B, E, C, N, ld, alpha, beta, gamma, sums, tile,
+                             (hipStream_t)stream);
 }
 
 int fdm_band_energy(const double *H, int64_t ldh, const double *D, int64_t ldd, int64_t N,

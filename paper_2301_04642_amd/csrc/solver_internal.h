@@ -28,6 +28,7 @@ struct Layout {
     int64_t part_cap = 0;
 };
 Layout plan_layout(int64_t n, bool finite, int prec);
+Layout plan_product_layout(int64_t n, int prec);
 
 // Per host thread and device: the cached workspace, the mapped host mirror
 // of the device state, and events.
@@ -55,10 +56,17 @@ struct Resources {
     ~Resources();
     int init(int dev);
     int bind(const Layout &L, void *user_mem, size_t user_bytes, hipStream_t s);
+    void view(const Layout &L, char *mem);  // points the buffers into mem (no other effect)
     hipEvent_t timing_event(size_t i);
     DevState *st_host();
 };
 Resources *thread_resources(int dev);
+
+bool sym_product_args_ok(int32_t precision, const double *A, const double *B, const double *E,
+                         const double *C, int64_t N, int64_t ld, int32_t tile);
+int sym_product_bound(Resources *r, int32_t precision, const double *A, const double *B,
+                      const double *E, double *C, int64_t N, int64_t ld, double alpha,
+                      double beta, double gamma, double *sums, int32_t tile, hipStream_t s);
 
 int hip_fail(hipError_t e, const char *what);
 const char *last_error();

@@ -66,30 +66,71 @@ def test_outliers_n30000_mixed(fdm, outliers30000, prec, bounds):
     sampled_checks(wl, d, f, rows, tol_rows=1e-4, tol_idem=1e-8)
 
 
-def test_uniform_n12000_finite_t_mixed(fdm):
-    """N = 12000, uniform [-1, 1], kT = 0.0016 Ha, n_occ = 3000: FP16x3 mu
-    search, one FP64 evaluation and the first-order trace correction."""
-    from oracle import density as den
+@pytest.fixture(scope="module")
+def uniform12000():
     say("generate uniform N=12000")
-    wl = workloads.standard_workload("uniform")
+    return workloads.standard_workload("uniform")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x3", "bf16x3"])
+def test_uniform_n12000_finite_t(fdm, uniform12000, prec):
+    """N = 12000, uniform [-1, 1], kT = 0.0016 Ha, n_occ = 3000 (Sec. II.A
+    Fermi-Dirac occupations; the paper's 500 K of Sec. IV).  FP64: every mu
+    evaluation in FP64, gated at 1e-10.  Mixed: the mu search in the low
+    precision, one FP64 evaluation, then the second-order canonical
+    correction; gated at |dE| <= 1e-6 Ha and |Tr D - n_occ| <= 1e-8.
+    Sampled rows of D against rows of Q f(Lambda) Q^T."""
+    from oracle import density as den
+    wl = uniform12000
     H = dev(wl.hp)
-    say("solve uniform N=12000 fp16x3")
-    D, e, st = fdm.solve(H, wl.n_occ, wl.kT, 1e-6, "fp16x3")
+    tol = 1e-10 if prec == "fp64" else 1e-8
+    # The doubling recursion's truncation error per state falls 4x per extra
+    # step and sums over all N states in the energy: at the default depth
+    # (+7) it leaves 1.4e-10 Ha here, at +8 a quarter of that.
+    extra = dict(fd_extra_depth=8) if prec == "fp64" else {}
+    say("solve uniform N=12000", prec)
+    D, e, st = fdm.solve(H, wl.n_occ, wl.kT, tol, prec, **extra)
+    del H
     d = host(D)
+    del D
     f, mu = den.occupations(wl.lam, wl.n_occ, wl.kT)
     e_ref = float(np.dot(f, wl.lam))
-    print(f"[report] uniform-n12000: evals={st.mu_evals} depth={st.depth} mu={st.mu:.9f} (exact {mu:.9f}) "
-          f"|dE|={abs(e - e_ref):.2e} |dTr|={abs(np.trace(d) - wl.n_occ):.2e} "
-          f"products fp64 {st.products[0]} fp16x3 {st.products[2]} {st.ms_total:.0f} ms", flush=True)
+    print(f"[report] uniform-n12000 {prec}: evals={st.mu_evals} depth={st.depth} mu={st.mu:.9f} "
+          f"(exact {mu:.9f}) |dE|={abs(e - e_ref):.2e} |dTr|={abs(np.trace(d) - wl.n_occ):.2e} "
+          f"products fp64 {st.products[0]} {prec} {st.products[fdm.PRECISIONS[prec]]} "
+          f"{st.ms_total:.0f} ms", flush=True)
     assert st.status == 0
-    assert abs(e - e_ref) <= 1e-6
-    assert abs(np.trace(d) - wl.n_occ) <= 1e-6
+    assert abs(e - e_ref) <= (1e-10 if prec == "fp64" else 1e-6)
+    assert abs(np.trace(d) - wl.n_occ) <= tol
     rows = np.random.default_rng(2).choice(wl.n, 6, replace=False)
-    from oracle import density as den2
-    ref_rows = den2.density_rows(wl.q_rows, wl.n, f, rows)
+    ref_rows = den.density_rows(wl.q_rows, wl.n, f, rows)
     err = np.abs(d[rows] - ref_rows).max()
     hr = wl.hp[rows]
     comm = np.linalg.norm(hr @ d - d[rows] @ wl.hp)
-    print(f"[report] uniform-n12000: sampled-row max err {err:.2e}, row commutator {comm:.2e}", flush=True)
-    assert err <= 1e-5
-    assert comm <= 1e-6
+    print(f"[report] uniform-n12000 {prec}: sampled-row max err {err:.2e}, row commutator "
+          f"{comm:.2e}", flush=True)
+    assert err <= (1e-10 if prec == "fp64" else 1e-5)
+    assert comm <= (1e-10 if prec == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp16x3", "bf16x3"])
+def test_uniform_n12000_bulk_low_precision_reported(fdm, uniform12000, prec):
+    """The finite-temperature form with every evaluation in low precision
+    (fd_final_fp64 = 0).  The doubling recursion amplifies rounding injected
+    near mu, so this form is not expected to meet the 1e-6 Ha gate: measured
+    and reported, with only the solve's status and the trace (set by the
+    final correction) checked."""
+    from oracle import density as den
+    wl = uniform12000
+    say("solve uniform N=12000 bulk", prec)
+    D, e, st = fdm.solve(dev(wl.hp), wl.n_occ, wl.kT, 1e-8, prec, fd_final_fp64=0)
+    tr = float(D.diagonal().sum())
+    del D
+    f, _ = den.occupations(wl.lam, wl.n_occ, wl.kT)
+    e_ref = float(np.dot(f, wl.lam))
+    print(f"[report] uniform-n12000 bulk {prec} (no FP64 evaluation): evals={st.mu_evals} "
+          f"|dE|={abs(e - e_ref):.2e} Ha (gate 1e-6: {'met' if abs(e - e_ref) <= 1e-6 else 'missed'}) "
+          f"|dTr|={abs(tr - wl.n_occ):.2e} {st.ms_total:.0f} ms", flush=True)
+    assert st.status == 0
+    assert st.products[0] <= 2        # only the canonical correction's two FP64 products
+    assert abs(tr - wl.n_occ) <= 1e-3

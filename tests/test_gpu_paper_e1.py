@@ -149,19 +149,44 @@ def test_e1_paper_sizes_zero_t(fdm, n):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("n", [16384])
+def test_e1_paper_sizes_finite_t(fdm, n):
+    """Sec. IV at finite temperature: 85% filling at 500 K on the paper's
+    matrix, FP16x3 mu search + one FP64 evaluation, against the golden
+    reference (banded eigensolver, exact Fermi-Dirac occupations)."""
+    import torch
+    g = golden(n)
+    n_occ = g["finite_t_n_occ"][0] if "finite_t_n_occ" in g else 0.85 * n
+    e_ref = g["finite_t_band_energy"][0]
+    mu_ref = g["finite_t_mu"][0]
+    say("E1 build", n)
+    H = e1_device(n)
+    say("E1 finite-T", n, "fp16x3")
+    D, e, st = fdm.solve(H, n_occ, workloads.gen.KT_500K, 1e-8, "fp16x3")
+    tr = float(torch.trace(D))
+    print(f"[report] E1 N={n} finite-T fp16x3: evals {st.mu_evals} depth {st.depth} "
+          f"mu={st.mu:.9f} (exact {mu_ref:.9f}) |dE|={abs(e - e_ref):.2e} "
+          f"|dTr|={abs(tr - n_occ):.2e} products fp64 {st.products[0]} fp16x3 {st.products[2]} "
+          f"{st.ms_total:.0f} ms", flush=True)
+    assert st.status == 0
+    assert abs(tr - n_occ) <= 1e-8
+    assert abs(e - e_ref) <= 1e-6
+    del D, H
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("accelerated", [False, True])
 def test_e1_n65536_zero_t_one_gpu(fdm, accelerated):
     """The paper's largest size, N = 65536 (the paper needed 2 nodes of 6 GPUs
     for it), on one GPU: Hp, D and the FP16x3 working set take about 230 GiB
-    of the 288 GB.  Plain SP2 or the accelerated form (HOMO/LUMO bounds 25%
-    inside the gap), checked against the banded-eigensolver reference.
-    Each case runs 1-2 minutes and holds most of the device memory, so it
-    runs only when FDM_RUN_N65536=1."""
+    of the 288 GB.  Plain SP2 (always run, 1-2 minutes) or the accelerated
+    form (HOMO/LUMO bounds 25% inside the gap; only when FDM_RUN_N65536=1),
+    checked against the banded-eigensolver reference."""
     import os
     import torch
     n = 65536
-    if os.environ.get("FDM_RUN_N65536") != "1":
-        pytest.skip("N = 65536 runs only with FDM_RUN_N65536=1 (1-2 minutes, ~230 GiB)")
+    if accelerated and os.environ.get("FDM_RUN_N65536") != "1":
+        pytest.skip("the accelerated N = 65536 case runs only with FDM_RUN_N65536=1")
     if not os.path.exists(os.path.join(os.path.dirname(__file__), "golden", f"e1_n{n}.txt")):
         pytest.skip("golden reference e1_n65536.txt not written (make_golden.py --large 65536)")
     g = golden(n)

@@ -12,7 +12,13 @@ Prints one JSON line.  `value` is the solves/s of the headline mixed form
 plain FP64 SP2; every measured form (fp64, fp32, fp16x3, bf16x3, with
 Gershgorin or Lanczos-tightened bounds, and the accelerated expansion "+az"
 given the HOMO/LUMO bounds an earlier solve estimated) is listed under
-"forms".
+"forms", each with the Sec. III.C metrics of its last solve (eps1, eps2,
+||D - D_ref||_F, |Tr D - n_occ|, idempotency, RelTr).  Two extra legs follow
+(skipped with --no-legs): "latency_n256", the single N = 256 FP64 solve in
+microseconds, and "serving", the continuous-batching server on 32 requests
+with N log-uniform in [500, 16000] (half gapped at kT = 0, half metallic at
+kT = 0.0016 Ha), FP32 and BF16x3, closed loop and then Poisson arrivals at
+0.8 x capacity (p50 / p99 latency), against one-at-a-time FP64 solves.
 """
 import argparse
 import json
@@ -97,7 +103,21 @@ def time_form(fdm, torch, H, wl, form, steps, warmup, e_ref, timing):
     dt = time.perf_counter() - t0
     return dict(prec=prec, bounds=bounds, seconds=dt, solves_per_s=steps / dt, ms_per_solve=1e3 * dt / steps,
                 worst_dE=worst_de, worst_idem=worst_idem, stats=last, prod_ms=agg_ms,
-                prod_n=agg_n, prod_flops=agg_flops, homo_lumo=homo_lumo)
+                prod_n=agg_n, prod_flops=agg_flops, homo_lumo=homo_lumo,
+                d_host=D.cpu().numpy(), e_last=e)
+
+
+def quality(d, e, st, n_occ, d_ref, e_ref):
+    """Sec. III.C metrics of one result against the reference projector:
+    ||D - D_ref||_F, eps1 = ||D - D_ref||_F / ||D_ref||_F, eps2 = (E - E_ref) /
+    E_ref, |Tr D - n_occ|, the idempotency the last product measured, and
+    the relative trace change RelTr of the last SP2 step."""
+    import numpy as np
+    dd = float(np.linalg.norm(d - d_ref))
+    return dict(D_minus_Dref_F=dd, eps1=dd / float(np.linalg.norm(d_ref)),
+                eps2=(e - e_ref) / e_ref, abs_dE_Ha=abs(e - e_ref),
+                trace_err=abs(float(np.trace(d)) - n_occ), idempotency=st.idempotency,
+                rel_trace=st.rel_trace)
 
 
 def cpu_baseline(wl, iters_per_solve, budget_s=15.0):
@@ -135,16 +155,54 @@ def cpu_baseline(wl, iters_per_solve, budget_s=15.0):
     return dict(value=value, unit="solves/s", cores=int(cores), kind="oracle", sample=sample)
 
 
-def serving(args):
-    """Continuous-batching server under Poisson arrivals: p50/p99 latency and
-    solves/s, against one-at-a-time FP64 solves of the same requests."""
+def latency_leg(fdm, torch, solves=200):
+    """The single small solve: N = 256, n_occ = 64, gap 0.2 Ha, plain FP64
+    SP2 (Gershgorin and certified-Lanczos bounds), microseconds per solve
+    with Hp resident, and the result against the oracle's projector."""
+    import numpy as np
+    import workloads
+    from oracle import density as den
+    wl = workloads.standard_workload("gapped")
+    f, _ = den.occupations(wl.lam, wl.n_occ, 0.0)
+    d_ref, e_ref = den.density_from_eig(wl.q, wl.lam, f)
+    H = torch.from_numpy(wl.hp).cuda()
+    D = torch.empty_like(H)
+    out = {}
+    for name, bounds in (("gershgorin", 0), ("lanczos", 1)):
+        opt = fdm.fdm_options_default()
+        opt.bounds = bounds
+        for _ in range(10):
+            fdm.fermi_dm_solve(H, wl.n_occ, 0.0, 1e-10, D, opt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(solves):
+            rc, e, st = fdm.fermi_dm_solve(H, wl.n_occ, 0.0, 1e-10, D, opt)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        q = quality(D.cpu().numpy(), e, st, wl.n_occ, d_ref, e_ref)
+        out[name] = dict(us_per_solve=round(1e6 * dt / solves, 1),
+                         solves_per_s=round(solves / dt, 1), products=st.iters_fp64 + 1,
+                         **{k: (float(f"{v:.3e}") if isinstance(v, float) else v)
+                            for k, v in q.items()})
+        log(f"latency n=256 fp64 {name}: {out[name]['us_per_solve']} us/solve "
+            f"||dD||={q['D_minus_Dref_F']:.1e}")
+    return dict(workload="gapped-n256-nocc64-gap0.2", precision="fp64", solves=solves, **out)
+
+
+def serving(args, precisions=None, log_every=8):
+    """Continuous-batching server under Poisson arrivals: closed-loop
+    capacity, then an open loop at args.load x capacity (p50/p99 latency,
+    solves/s), for each served precision, against one-at-a-time FP64 solves
+    of the same requests.  Returns a dict."""
     import numpy as np
     import torch
 
     import paper_2301_04642_amd as fdm
     import workloads
+    from oracle import density as den
 
     torch.cuda.set_device(0)
+    precisions = precisions or [args.serve_precision]
     rng = np.random.default_rng(4_999_999)
     ntemp = 6
     ns = sorted(set(int(x) for x in np.exp(rng.uniform(np.log(args.n_min), np.log(args.n_max),
@@ -157,7 +215,6 @@ def serving(args):
                        kT=0.0 if kind == "gapped" else workloads.gen.KT_500K, seed=5_000_000 + 7 * i)
             log(f"  template n={n} {kind}")
             wl = workloads.serving_workload(req)
-            from oracle import density as den
             f, _ = den.occupations(wl.lam, wl.n_occ, wl.kT)
             templates[(n, kind)] = (wl, float(np.dot(f, wl.lam)))
     reqs = []
@@ -170,64 +227,68 @@ def serving(args):
         hp = (wl.hp[np.ix_(perm, perm)] * sign[:, None]) * sign[None, :]
         reqs.append(dict(n=n, n_occ=wl.n_occ, kT=wl.kT, hp=np.ascontiguousarray(hp), e_ref=e_ref))
     budget = int(args.budget_gb * (1 << 30))
+    arrival_rng = np.random.default_rng(4_999_998)
 
-    def run(arrivals):
-        srv = fdm.Server(budget_bytes=budget, max_active=args.max_active,
-                         precision=args.serve_precision)
+    def run(arrivals, prec):
+        srv = fdm.Server(budget_bytes=budget, max_active=args.max_active, precision=prec)
         t0 = time.perf_counter()
         tickets = []
         for q, at in zip(reqs, arrivals):
             while time.perf_counter() - t0 < at:
                 time.sleep(0.0005)
-            tickets.append((srv.submit(q["hp"], q["n_occ"], q["kT"], 1e-8), time.perf_counter() - t0))
+            tickets.append(srv.submit(q["hp"], q["n_occ"], q["kT"], 1e-8))
         lat, worst = [], 0.0
-        t_end = 0.0
-        for k, ((t, t_sub), q) in enumerate(zip(tickets, reqs)):
-            if k % 4 == 0:
+        for k, (t, q) in enumerate(zip(tickets, reqs)):
+            if k % log_every == 0:
                 log(f"  collecting result {k} / {len(reqs)}")
             rc, d, e, st, times = srv.result(t, q["n"])
             assert rc == 0, rc
             worst = max(worst, abs(e - q["e_ref"]))
             lat.append(times[2] - times[0])
-            t_end = max(t_end, times[2])
+        held, _, _ = srv.memory()
         srv.close()
-        return np.array(lat), worst, time.perf_counter() - t0
+        return np.array(lat), worst, time.perf_counter() - t0, held
 
-    log("closed loop (all requests at t = 0)")
-    lat0, worst0, span0 = run([0.0] * len(reqs))
-    capacity = len(reqs) / span0
-    rate = args.load * capacity
-    gaps = rng.exponential(1.0 / rate, len(reqs))
-    arrivals = list(np.cumsum(gaps) - gaps[0])
-    log(f"open loop at {args.load} x capacity = {rate:.2f} requests/s")
-    lat, worst, span = run(arrivals)
+    per_prec = {}
+    for prec in precisions:
+        log(f"serving {prec}: closed loop (all requests at t = 0)")
+        lat0, worst0, span0, held0 = run([0.0] * len(reqs), prec)
+        capacity = len(reqs) / span0
+        rate = args.load * capacity
+        gaps = arrival_rng.exponential(1.0 / rate, len(reqs))
+        arrivals = list(np.cumsum(gaps) - gaps[0])
+        log(f"serving {prec}: open loop at {args.load} x capacity = {rate:.2f} requests/s")
+        lat, worst, span, held = run(arrivals, prec)
+        per_prec[prec] = {
+            "closed_loop_solves_per_s": round(capacity, 3),
+            "closed_loop_p50_s": round(float(np.percentile(lat0, 50)), 4),
+            "closed_loop_p99_s": round(float(np.percentile(lat0, 99)), 4),
+            "open_loop": {"offered_rate": round(rate, 3),
+                          "solves_per_s": round(len(reqs) / span, 3),
+                          "p50_s": round(float(np.percentile(lat, 50)), 4),
+                          "p99_s": round(float(np.percentile(lat, 99)), 4),
+                          "mean_s": round(float(lat.mean()), 4)},
+            "worst_abs_dE_Ha": max(worst, worst0),
+            "held_device_bytes_at_end": max(held, held0),
+        }
     log("one at a time, fp64")
-    H = None
     t0 = time.perf_counter()
     for k, q in enumerate(reqs):
-        if k % 4 == 0:
+        if k % log_every == 0:
             log(f"  request {k} / {len(reqs)}")
         H = torch.from_numpy(q["hp"]).cuda()
         fdm.solve(H, q["n_occ"], q["kT"], 1e-8, "fp64")
     torch.cuda.synchronize()
     seq = len(reqs) / (time.perf_counter() - t0)
-    out = {
+    return {
         "metric": "serving: solves/s and latency under Poisson arrivals", "unit": "solves/s",
         "requests": len(reqs), "n_range": [args.n_min, args.n_max], "distinct_n": ns,
-        "precision": args.serve_precision, "max_active": args.max_active,
-        "budget_gb": args.budget_gb,
-        "closed_loop_solves_per_s": round(capacity, 3),
-        "open_loop": {"offered_rate": round(rate, 3), "solves_per_s": round(len(reqs) / span, 3),
-                      "p50_s": round(float(np.percentile(lat, 50)), 4),
-                      "p99_s": round(float(np.percentile(lat, 99)), 4),
-                      "mean_s": round(float(lat.mean()), 4)},
-        "closed_loop_p50_s": round(float(np.percentile(lat0, 50)), 4),
-        "closed_loop_p99_s": round(float(np.percentile(lat0, 99)), 4),
+        "max_active": args.max_active, "budget_gb": args.budget_gb, "load": args.load,
+        "forms": per_prec,
         "sequential_fp64_solves_per_s": round(seq, 3),
-        "worst_abs_dE_Ha": max(worst, worst0),
-        "data": "synthetic (signed permutations of seeded templates)",
+        "data": "synthetic (signed permutations of seeded templates; half gapped 0.1 Ha at "
+                "kT = 0, half metallic at kT = 0.0016 Ha)",
     }
-    print(json.dumps(out))
 
 
 def main():
@@ -255,11 +316,18 @@ def main():
                     help="precision of the served solves (fp16x3: 50.5 vs fp32 38.9 solves/s)")
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--load", type=float, default=0.8)
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the N = 256 latency leg and the compact serving leg")
+    ap.add_argument("--latency-only", action="store_true",
+                    help="run only the N = 256 latency leg and print its JSON")
+    ap.add_argument("--leg-requests", type=int, default=32,
+                    help="requests of the compact serving leg (N log-uniform in [500, 16000])")
     args = ap.parse_args()
     if args.serving:
         if args.gpus != 1:
             sys.exit("serving runs on one GPU")
-        return serving(args)
+        print(json.dumps(serving(args)))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the solver has no multi-GPU path "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
@@ -272,6 +340,9 @@ def main():
     import workloads
 
     torch.cuda.set_device(0)
+    if args.latency_only:
+        print(json.dumps(latency_leg(fdm, torch, solves=args.steps)))
+        return
     if args.calib_copy_mib:
         nel = args.calib_copy_mib * (1 << 20) // 8
         src = torch.ones(nel, dtype=torch.float64, device="cuda")
@@ -284,6 +355,9 @@ def main():
     log("generating workload")
     wl = workloads.standard_workload("bands", n=args.n)
     e_ref = float(np.sort(wl.lam)[: int(wl.n_occ)].sum())   # sum of the n_occ lowest
+    occ = np.argsort(wl.lam, kind="stable")[: int(wl.n_occ)]
+    q_occ = wl.q_full()[:, occ]
+    d_ref = q_occ @ q_occ.T                                 # the reference projector
     H = torch.from_numpy(wl.hp).cuda()
     suffix = "+lanczos" if args.bounds == "lanczos" else ""
     head_form, ref_form = args.precision + suffix, "fp64" + suffix
@@ -329,7 +403,11 @@ def main():
             **({"homo_lumo_bounds": [round(x, 6) if x == x else None for x in r["homo_lumo"]],
                 "homo_lumo_source": "estimate_gap of an earlier solve (untimed)"}
                if r["homo_lumo"] else {}),
-            gate_pass=bool(r["worst_dE"] <= 1e-6 and r["worst_idem"] <= 1e-8))
+            gate_pass=bool(r["worst_dE"] <= 1e-6 and r["worst_idem"] <= 1e-8),
+            quality_last_solve={k: float(f"{v:.3e}") for k, v in
+                                quality(r["d_host"], r["e_last"], st, wl.n_occ, d_ref,
+                                        e_ref).items()})
+        r.pop("d_host")
     out = {
         "metric": "DM solves/s + X^2 GEMM TFLOP/s, mixed vs FP64 SP2, at |dE_band|<=1e-6 Ha",
         "value": round(head["solves_per_s"], 4),
@@ -356,7 +434,17 @@ def main():
                      "avg_launch_ms": round(avg_ms, 4),
                      "flops_per_launch": mult * per_product_flops},
         "forms": forms_out,
+        "extra_keys_note": "forms: every measured form with its quality_last_solve (Sec. III.C "
+                           "eps1, eps2 and the absolute gates); latency_n256: the single small "
+                           "FP64 solve; serving: the compact continuous-batching leg",
     }
+    if not args.no_legs:
+        log("latency leg")
+        out["latency_n256"] = latency_leg(fdm, torch)
+        log("compact serving leg")
+        leg = argparse.Namespace(**vars(args))
+        leg.requests, leg.n_min, leg.n_max = args.leg_requests, 500, 16000
+        out["serving"] = serving(leg, precisions=["fp32", "bf16x3"])
     if not args.no_cpu:
         # the oracle runs its own plain FP64 SP2 with Gershgorin bounds; the
         # fp64 form's product count only sizes a partial run at large N

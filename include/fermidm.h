@@ -81,15 +81,16 @@ typedef struct fdm_options {
     int32_t timing;         /* 1: time every product launch with HIP events (0)                */
     int32_t tile;           /* product tile edge: 0 = automatic, or 64 / 128                   */
     int32_t bounds;         /* spectral bounds (Sec. II.C): 0 = Gershgorin discs; 1 (default)
-                               = Gershgorin tightened by a Lanczos estimate of the extreme
-                               eigenvalues (Ritz values widened by their residual bounds and
-                               1% of the width), widened by N^(1/64) * 1.03 about their centre
-                               and then certified: with A = (Hp - c I) / r for the interval
-                               c -+ r, ||A^32||_F^(1/32) (five FP16x3 products, with the
-                               rounding error of each bounded) must prove every eigenvalue of
-                               A inside [-1, 1]; otherwise the Gershgorin interval is used
-                               (stats.bounds_certified = -1).  Never outside the Gershgorin
-                               interval.                                                      */
+                               = a Lanczos estimate of the extreme eigenvalues (Ritz values
+                               widened by their residual bounds and 1% of the width), interval
+                               c -+ r, then certified: with A = (Hp - c I) / r, the powers
+                               A^2, A^4, ..., A^32 (five FP16x3 products, the rounding of
+                               each bounded) give b >= max |lambda(A)| from ||A^32||_F, and
+                               c -+ b r is used (so an eigenvalue the estimate missed widens
+                               the interval; b <= N^(1/64) max |lambda(A)|).  Powers that
+                               overflow FP16 (max |lambda(A)| well above 1) fall back to the
+                               Gershgorin interval (stats.bounds_certified = -1).  Never
+                               outside the Gershgorin interval.                              */
     int32_t lanczos_steps;  /* Lanczos steps for bounds = 1 (default 16, at most 64)           */
     int32_t estimate_gap;   /* zero T: 1 = after the solve, estimate bounds on the HOMO and LUMO
                                eigenvalues for a later accelerated solve (stats homo_ub /

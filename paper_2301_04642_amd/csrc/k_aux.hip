@@ -380,6 +380,7 @@ __global__ __launch_bounds__(256) void k_decide(DevState *st, HostMirror *hm,
     s0 = red[0][0];
     s1 = red[1][0];
     s2 = red[2][0];
+    const int32_t was_done = st->done;
     switch (mode) {
         case D_INIT:
             st->trace = s0;
@@ -498,9 +499,11 @@ __global__ __launch_bounds__(256) void k_decide(DevState *st, HostMirror *hm,
             st->sums[2] = s2;
             break;
     }
-    if (hm != nullptr) {
-        // The host polls `done` and then reads the other fields: they are
-        // written first and made visible before `done` is.
+    if (hm != nullptr && st->done && !was_done) {
+        // Written once per phase, by the decision that ends it (the host
+        // clears `done` before the phase starts and polls it).  The host
+        // reads the other fields after it sees `done`: they are written
+        // first and made visible before `done` is.
         volatile HostMirror *vh = hm;
         vh->iter = st->iter;
         vh->result_iter = st->result_iter;

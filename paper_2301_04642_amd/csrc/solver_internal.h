@@ -30,6 +30,9 @@ struct Layout {
 Layout plan_layout(int64_t n, bool finite, int prec);
 Layout plan_product_layout(int64_t n, int prec);
 
+// Events of the steps in flight (one ring per host thread and device).
+constexpr int kEvRing = 8;
+
 // Per host thread and device: the cached workspace, the mapped host mirror
 // of the device state, and events.
 struct Resources {
@@ -50,7 +53,7 @@ struct Resources {
     HostMirror *hm_host = nullptr, *hm_dev = nullptr;
     DevState *st_pinned = nullptr;
     DevState st_fallback;
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t ev[kEvRing] = {};
     std::vector<hipEvent_t> tev;
 
     ~Resources();

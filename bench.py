@@ -230,7 +230,8 @@ def serving(args, precisions=None, log_every=8):
     arrival_rng = np.random.default_rng(4_999_998)
 
     def run(arrivals, prec):
-        srv = fdm.Server(budget_bytes=budget, max_active=args.max_active, precision=prec)
+        srv = fdm.Server(budget_bytes=budget, max_active=args.max_active, precision=prec,
+                         grouped=not args.serve_independent)
         t0 = time.perf_counter()
         tickets = []
         for q, at in zip(reqs, arrivals):
@@ -284,6 +285,8 @@ def serving(args, precisions=None, log_every=8):
         "metric": "serving: solves/s and latency under Poisson arrivals", "unit": "solves/s",
         "requests": len(reqs), "n_range": [args.n_min, args.n_max], "distinct_n": ns,
         "max_active": args.max_active, "budget_gb": args.budget_gb, "load": args.load,
+        "ticks": "independent streams" if args.serve_independent else
+                 "grouped (one product launch per precision and one decision launch per tick)",
         "forms": per_prec,
         "sequential_fp64_solves_per_s": round(seq, 3),
         "data": "synthetic (signed permutations of seeded templates; half gapped 0.1 Ha at "
@@ -315,6 +318,8 @@ def main():
     ap.add_argument("--serve-precision", default="fp16x3", choices=["fp32", "fp16x3", "bf16x3"],
                     help="precision of the served solves (fp16x3: 50.5 vs fp32 38.9 solves/s)")
     ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--serve-independent", action="store_true",
+                    help="serve with each request on its own stream (no grouped ticks)")
     ap.add_argument("--load", type=float, default=0.8)
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the N = 256 latency leg and the compact serving leg")

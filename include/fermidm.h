@@ -186,6 +186,10 @@ typedef struct fdm_stats {
                                    canonical correction, energy, copy-out)                    */
     int32_t trfoe_depth;        /* finite T with trfoe = 1: SP2 steps of the truncated expansion */
     int32_t reltr_schedule;     /* zero T: 1 when the paper's RelTr schedule produced D        */
+    int32_t tick_steps;         /* served with grouped ticks: hot-loop steps of this solve that
+                                   ran in ticks (0 outside a server)                           */
+    int32_t tick_shared;        /* of them, steps that shared their tick (grouped product and
+                                   decision launches) with another request's step              */
 } fdm_stats;
 
 /* Fills *opt with the defaults listed above.  Returns FDM_EINVAL if opt is NULL. */
@@ -308,8 +312,15 @@ typedef struct fdm_server fdm_server;
 
 typedef struct fdm_server_options {
     size_t budget_bytes;    /* device memory the server may hold for resident requests      */
-    int32_t max_active;     /* requests executing at once (each on its own stream); 0 = 4    */
+    int32_t max_active;     /* requests executing at once (each on its own host thread and
+                               stream); 0 = 4, at most 16                                    */
     int32_t precision;      /* default precision of submitted requests                      */
+    int32_t independent;    /* 0 (default): the hot-loop steps of the executing requests (SP2
+                               and McWeeny products, finite-temperature evaluations) run in
+                               ticks, one grouped product launch per precision and one grouped
+                               decision per tick over all of them; 1: each request launches
+                               on its own stream                                              */
+    int32_t reserved;
 } fdm_server_options;
 
 /* Creates a server on the current device (the caller selects it with

@@ -66,7 +66,8 @@ class fdm_stats(ctypes.Structure):
                 ("idem_tail_len", ctypes.c_int32), ("bounds_certified", ctypes.c_int32),
                 ("lanczos_min", ctypes.c_double), ("lanczos_max", ctypes.c_double),
                 ("cert_radius", ctypes.c_double), ("phase_ms", ctypes.c_double * 4),
-                ("trfoe_depth", ctypes.c_int32), ("reltr_schedule", ctypes.c_int32)]
+                ("trfoe_depth", ctypes.c_int32), ("reltr_schedule", ctypes.c_int32),
+                ("tick_steps", ctypes.c_int32), ("tick_shared", ctypes.c_int32)]
 
     def as_dict(self):
         d = {}
@@ -81,7 +82,8 @@ class fdm_stats(ctypes.Structure):
 
 class fdm_server_options(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int32),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("independent", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class FdmError(RuntimeError):
@@ -294,9 +296,10 @@ def fdm_fermi_operator(H, mu, kT, D, depth=0, precision=FDM_FP64, stream=None):
 class Server:
     """Continuous-batching server (fdm_server_* of the C ABI)."""
 
-    def __init__(self, budget_bytes, max_active=4, precision="fp32"):
+    def __init__(self, budget_bytes, max_active=4, precision="fp32", grouped=True):
         o = fdm_server_options(int(budget_bytes), int(max_active),
-                               PRECISIONS[precision] if isinstance(precision, str) else precision)
+                               PRECISIONS[precision] if isinstance(precision, str) else precision,
+                               0 if grouped else 1, 0)
         self._s = _lib.fdm_server_create(ctypes.byref(o))
         if not self._s:
             raise FdmError(FDM_EINVAL, "fdm_server_create: " + fdm_last_error())

@@ -108,6 +108,34 @@ struct ProdArgs {
 // ---- launchers (k_symprod.hip, k_aux.hip) --------------------------------
 hipError_t launch_symprod(int prec, int bt, const ProdArgs &a, hipStream_t s);
 
+// Grouped launches of the serving tick: up to kMaxGroup products of one
+// precision, tile edge and staging path (their tile lists concatenated),
+// and up to kMaxGroup decisions (one block each).  Passed by value as
+// kernel arguments.
+constexpr int kMaxGroup = 16;
+struct ProdGroup {
+    int32_t njobs;
+    int32_t first[kMaxGroup + 1];  // job j owns grid entries [first[j], first[j+1])
+    ProdArgs job[kMaxGroup];
+};
+// The staging path launch_symprod takes for (prec, bt, ld): products are
+// grouped only with others of the same path.
+bool symprod_direct(int prec, int bt, int64_t ld);
+hipError_t launch_symprod_grouped(int prec, int bt, bool direct, const ProdGroup &g,
+                                  hipStream_t s);
+
+struct DecideJob {
+    DevState *st;
+    HostMirror *hm;
+    const double *part;
+    int32_t count, mode, stride, pad;
+};
+struct DecideGroup {
+    int32_t njobs, pad;
+    DecideJob job[kMaxGroup];
+};
+hipError_t launch_decide_grouped(const DecideGroup &g, hipStream_t s);
+
 // out = a * in + b * I on [0,n)^2, zeros on [0,np)^2 outside; in may be a
 // double (caller layout) or a float/double working matrix.  When zt_init is
 // set, (a, b) come from the Gershgorin bounds in st: a = -1/(emax-emin),

@@ -143,9 +143,18 @@ int Ctx::fermi_operator(const double *Hp, int64_t ldh, double mu, int depth, int
         buf[i] = lo ? (void *)(r->x32 + i * m) : (void *)(r->x64 + i * m);
     const double beta = 1.0 / kT;
     const double c0 = ldexp(beta, -(depth + 2));
-    // Y_0 = c0 (H - mu I)
-    int rc = affine(0, Hp, ldh, lo ? 1 : 0, buf[0], c0, -c0 * mu, 0, nullptr);
+    // In a serving tick group the evaluation's launches are recorded and run
+    // grouped with other solves' steps; the host waits once, before reading
+    // the sums.
+    int rc = begin_stream_capture();
     if (rc) return rc;
+    auto fail = [&](int code) {
+        end_stream_capture();
+        return code;
+    };
+    // Y_0 = c0 (H - mu I)
+    rc = affine(0, Hp, ldh, lo ? 1 : 0, buf[0], c0, -c0 * mu, 0, nullptr);
+    if (rc) return fail(rc);
     void *Y = buf[0], *S = buf[1], *Z = buf[2], *Z2 = buf[3], *W = buf[4];
     // closed-form bound of ||Y_k||: (1/2) tanh(2^k atanh(2 ||Y_0||))
     const double y0 = c0 * std::max(stats.e_max - mu, mu - stats.e_min);
@@ -159,27 +168,29 @@ int Ctx::fermi_operator(const double *Hp, int64_t ldh, double mu, int depth, int
         const double t = tanh(ldexp(a0, k));
         const double rk = std::min(t * t, 1.0);
         rc = product(prec, Y, Y, nullptr, S, c_sq, nullptr, false, false);
-        if (rc) return rc;
+        if (rc) return fail(rc);
         const NsStart z1 = ns_start(rk);
         rc = affine(lo ? 1 : 0, S, r->lay.ld, lo ? 1 : 0, Z, z1.a, z1.b, 0, nullptr);
-        if (rc) return rc;
+        if (rc) return fail(rc);
         const int J = ns_iterations(z1.e1, target);
         for (int j = 0; j < J; ++j) {
             rc = product(prec, S, Z, Z, W, c_w, nullptr, false, false);
-            if (rc) return rc;
+            if (rc) return fail(rc);
             rc = product(prec, Z, W, Z, Z2, c_z, nullptr, false, false);
-            if (rc) return rc;
+            if (rc) return fail(rc);
             std::swap(Z, Z2);
         }
         rc = product(prec, Y, Z, nullptr, S, c_y, nullptr, false, false);
-        if (rc) return rc;
+        if (rc) return fail(rc);
         std::swap(Y, S);
     }
     // D = I/2 - Y_m, with Tr D and ||D||_F^2
     int np = 0;
     rc = affine(lo ? 1 : 0, Y, r->lay.ld, lo ? 1 : 0, S, -1.0, 0.5, 0, &np);
-    if (rc) return rc;
+    if (rc) return fail(rc);
     rc = decide(D_SUMS, np, 4);
+    if (rc) return fail(rc);
+    rc = end_stream_capture();
     if (rc) return rc;
     // every product of this evaluation ran (no device-side early exit)
     close_phase((int)phase_launches.size());

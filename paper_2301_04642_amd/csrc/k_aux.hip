@@ -351,9 +351,9 @@ __device__ __forceinline__ int choose_square(double trace, double fro2, double n
     return fabs(fro2 - n_occ) <= fabs(2.0 * trace - fro2 - n_occ) ? 1 : 0;
 }
 
-__global__ __launch_bounds__(256) void k_decide(DevState *st, HostMirror *hm,
-                                                const double *__restrict__ part, int count,
-                                                int mode, int stride) {
+__device__ __forceinline__ void decide_block(DevState *st, HostMirror *hm,
+                                             const double *__restrict__ part, int count, int mode,
+                                             int stride) {
     if ((mode == D_SP2 || mode == D_MCW_T || mode == D_MCW_OUT) && st->done) return;
     __shared__ double red[3][256];
     const int t = threadIdx.x;
@@ -518,6 +518,19 @@ __global__ __launch_bounds__(256) void k_decide(DevState *st, HostMirror *hm,
     }
 }
 
+__global__ __launch_bounds__(256) void k_decide(DevState *st, HostMirror *hm,
+                                                const double *__restrict__ part, int count,
+                                                int mode, int stride) {
+    decide_block(st, hm, part, count, mode, stride);
+}
+
+// One block per decision (the serving tick); each block does exactly what
+// k_decide does for its job.
+__global__ __launch_bounds__(256) void k_decide_grouped(DecideGroup g) {
+    const DecideJob &j = g.job[blockIdx.x];
+    decide_block(j.st, j.hm, j.part, j.count, j.mode, j.stride);
+}
+
 // Parameters of the next phase; reset_all also clears the solve-wide fields.
 __global__ void k_set_params(DevState *st, double n_occ, double tol, double tau, int max_iter,
                              int switch_mode, int reset_all) {
@@ -574,6 +587,12 @@ hipError_t launch_affine(int in_f32, const void *in, int64_t ldi, int out_f32, v
         hipLaunchKernelGGL((k_affine<float, float>), dim3(nb), dim3(256), 0, s,
                            (const float *)in, ldi, (float *)out, ldo, n, np, a, b, zt_init, st,
                            partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_decide_grouped(const DecideGroup &g, hipStream_t s) {
+    if (g.njobs <= 0 || g.njobs > kMaxGroup) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_decide_grouped, dim3(g.njobs), dim3(256), 0, s, g);
     return hipGetLastError();
 }
 

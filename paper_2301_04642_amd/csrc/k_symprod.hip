@@ -201,17 +201,16 @@ __device__ __forceinline__ typename PT<P>::Acc mfma_frag(const u4_t &a, const u4
     return c;
 }
 
-// 64-wide tiles are register-capped to four waves per SIMD (four blocks per
-// CU); 128-wide FP64, FP32 and split tiles to two (two blocks per CU: 64 x 64
-// outputs per wave, half the panel and LDS fragment traffic per flop of a
-// 64-wide tile); the single-pass 16-bit 128-wide tiles run one wave per SIMD.
+// Workgroups go round-robin over the 8 XCDs: block b runs list entry
+// xcd_remap(b), so each XCD walks a contiguous run of the list.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int xcd = b & 7, slot = b >> 3, per = nb >> 3, rem = nb & 7;
+    return (xcd < rem) ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+}
+
+// One output tile (entry t of a.tiles) of one product.
 template <int P, int BT, bool DMA>
-__global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(
-    BT == 64 ? 4 : ((P == P_F32 || P == P_F64 || PT<P>::SPLIT) ? 2 : 1),
-    BT == 64 ? 4 : ((P == P_F32 || P == P_F64 || PT<P>::SPLIT) ? 2 : 1))))
-void k_symprod(ProdArgs a) {
-    if (a.done != nullptr && *a.done) return;
+__device__ __forceinline__ void symprod_tile(const ProdArgs &a, const int t) {
     using T = PT<P>;
     using S = typename T::S;
     using Acc = typename T::Acc;
@@ -240,10 +239,6 @@ void k_symprod(ProdArgs a) {
     __shared__ __attribute__((aligned(16))) unsigned char lds[2 * 2 * PANEL];
 
     const int tid = threadIdx.x;
-    const int nb = gridDim.x, b = blockIdx.x;
-    const int xcd = b & 7, slot = b >> 3, per = nb >> 3, rem = nb & 7;
-    const int t = (xcd < rem) ? xcd * (per + 1) + slot
-                              : rem * (per + 1) + (xcd - rem) * per + slot;
     const uint32_t tt = a.tiles[t];
     const int ti = (int)(tt >> 16), tj = (int)(tt & 0xffffu);
     const int64_t row0 = (int64_t)ti * BT, col0 = (int64_t)tj * BT;
@@ -570,6 +565,36 @@ void k_symprod(ProdArgs a) {
     }
 }
 
+// 64-wide tiles are register-capped to four waves per SIMD (four blocks per
+// CU); 128-wide FP64, FP32 and split tiles to two (two blocks per CU: 64 x 64
+// outputs per wave, half the panel and LDS fragment traffic per flop of a
+// 64-wide tile); the single-pass 16-bit 128-wide tiles run one wave per SIMD.
+#define FDM_SYMPROD_ATTRS(P, BT)                                                        \
+    __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(                          \
+        BT == 64 ? 4 : ((P == P_F32 || P == P_F64 || PT<P>::SPLIT) ? 2 : 1),             \
+        BT == 64 ? 4 : ((P == P_F32 || P == P_F64 || PT<P>::SPLIT) ? 2 : 1))))
+
+template <int P, int BT, bool DMA>
+__global__ FDM_SYMPROD_ATTRS(P, BT) void k_symprod(ProdArgs a) {
+    if (a.done != nullptr && *a.done) return;
+    symprod_tile<P, BT, DMA>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// Several products of one precision, tile edge and staging path in one
+// launch (the serving tick): the grid covers the concatenated tile lists,
+// job j owning list entries [first[j], first[j+1]).  Each tile is computed
+// exactly as by k_symprod, so a product's result does not depend on what it
+// was grouped with.
+template <int P, int BT, bool DMA>
+__global__ FDM_SYMPROD_ATTRS(P, BT) void k_symprod_grouped(ProdGroup g) {
+    const int u = xcd_remap(blockIdx.x, gridDim.x);
+    int j = 0;
+    while (j + 1 < g.njobs && u >= g.first[j + 1]) ++j;
+    const ProdArgs &a = g.job[j];
+    if (a.done != nullptr && *a.done) return;
+    symprod_tile<P, BT, DMA>(a, u - g.first[j]);
+}
+
 // Staging path (measured on MI355X, SP2 solves of the paper's matrix):
 //  * split forms, 64-wide tiles: direct to LDS (0.32 -> 0.26 ms per product
 //    at N = 4000);
@@ -583,12 +608,16 @@ void k_symprod(ProdArgs a) {
 constexpr int64_t kSplitDirectMaxLd = 18432;
 
 template <int P, int BT>
+bool direct_t(int64_t ld) {
+    if constexpr (PT<P>::SPLIT) return (BT == 64) || ld <= kSplitDirectMaxLd;
+    else if constexpr (P == P_F64 || P == P_F32) return BT == 128;
+    return false;
+}
+
+template <int P, int BT>
 hipError_t launch_t(const ProdArgs &a, hipStream_t s) {
     constexpr bool ok = (P == P_F64 || P == P_F32 || PT<P>::SPLIT);
-    bool direct = false;
-    if constexpr (PT<P>::SPLIT) direct = (BT == 64) || a.ld <= kSplitDirectMaxLd;
-    else if constexpr (ok) direct = (BT == 128);
-    if (direct)
+    if (direct_t<P, BT>(a.ld))
         hipLaunchKernelGGL((k_symprod<P, BT, ok>), dim3(a.ntiles), dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL((k_symprod<P, BT, false>), dim3(a.ntiles), dim3(256), 0, s, a);
@@ -601,7 +630,50 @@ hipError_t launch_p(int bt, const ProdArgs &a, hipStream_t s) {
     return launch_t<P, 64>(a, s);
 }
 
+template <int P, int BT>
+hipError_t launch_grouped_t(bool direct, const ProdGroup &g, int total, hipStream_t s) {
+    constexpr bool ok = (P == P_F64 || P == P_F32 || PT<P>::SPLIT);
+    if (direct && ok)
+        hipLaunchKernelGGL((k_symprod_grouped<P, BT, ok>), dim3(total), dim3(256), 0, s, g);
+    else
+        hipLaunchKernelGGL((k_symprod_grouped<P, BT, false>), dim3(total), dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_grouped_p(int bt, bool direct, const ProdGroup &g, int total, hipStream_t s) {
+    if (bt == 128) return launch_grouped_t<P, 128>(direct, g, total, s);
+    return launch_grouped_t<P, 64>(direct, g, total, s);
+}
+
 }  // namespace
+
+bool symprod_direct(int prec, int bt, int64_t ld) {
+    switch (prec) {
+        case P_F64: return bt == 128 ? direct_t<P_F64, 128>(ld) : direct_t<P_F64, 64>(ld);
+        case P_F32: return bt == 128 ? direct_t<P_F32, 128>(ld) : direct_t<P_F32, 64>(ld);
+        case P_F16X3: return bt == 128 ? direct_t<P_F16X3, 128>(ld) : direct_t<P_F16X3, 64>(ld);
+        case P_BF16X3:
+            return bt == 128 ? direct_t<P_BF16X3, 128>(ld) : direct_t<P_BF16X3, 64>(ld);
+        default: return false;
+    }
+}
+
+hipError_t launch_symprod_grouped(int prec, int bt, bool direct, const ProdGroup &g,
+                                  hipStream_t s) {
+    if (g.njobs <= 0 || g.njobs > kMaxGroup) return hipErrorInvalidValue;
+    const int total = g.first[g.njobs];
+    if (total <= 0) return hipSuccess;
+    switch (prec) {
+        case P_F64: return launch_grouped_p<P_F64>(bt, direct, g, total, s);
+        case P_F32: return launch_grouped_p<P_F32>(bt, direct, g, total, s);
+        case P_F16X3: return launch_grouped_p<P_F16X3>(bt, direct, g, total, s);
+        case P_BF16X3: return launch_grouped_p<P_BF16X3>(bt, direct, g, total, s);
+        case P_BF16: return launch_grouped_p<P_BF16>(bt, direct, g, total, s);
+        case P_F16: return launch_grouped_p<P_F16>(bt, direct, g, total, s);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_split(int prec, const float *x, uint16_t *hl, int64_t ld, int64_t rows,
                         hipStream_t s) {

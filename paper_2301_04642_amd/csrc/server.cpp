@@ -25,11 +25,15 @@
 #include <vector>
 
 #include "fdm_internal.h"
+#include "solver_internal.h"
 
 namespace fdm {
 namespace {
 
 using Clock = std::chrono::steady_clock;
+
+// Requests from this size up tick in the large-size group.
+constexpr int64_t kTickLargeN = 2048;
 
 struct Request {
     uint64_t id = 0;
@@ -138,6 +142,11 @@ struct fdm_server {
     BlockPool pool;                   // guarded by mu
     std::vector<std::thread> workers;
     std::thread admitter;
+    // grouped hot-loop steps, one tick group per size class (nullptr:
+    // independent streams): a tick lasts as long as its largest product, so
+    // small requests tick with small ones at their own pace, on their own
+    // stream, beside the large ones
+    TickGroup *group[2] = {nullptr, nullptr};
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 };
@@ -239,8 +248,8 @@ static void executor_loop(fdm_server *s) {
             opt.precision = r->precision;
             opt.workspace = ws;
             opt.workspace_bytes = cls[2];
-            rc = fermi_dm_solve(hp, r->n, r->n, r->n_occ, r->kT, r->tol, d, r->n, &r->e_band,
-                                &opt, &r->stats, stream);
+            rc = solve_impl(hp, r->n, r->n, r->n_occ, r->kT, r->tol, d, r->n, &r->e_band, &opt,
+                            &r->stats, stream, s->group[r->n >= kTickLargeN ? 1 : 0]);
         }
         hipStreamSynchronize(stream);
         lk.lock();
@@ -279,8 +288,22 @@ fdm_server *fdm_server_create(const fdm_server_options *opt) {
     }
     s->budget = opt->budget_bytes;
     s->max_active = opt->max_active > 0 ? opt->max_active : 4;
+    if (s->max_active > kMaxGroup) {
+        set_error("max_active above " + std::to_string(kMaxGroup));
+        return nullptr;
+    }
     s->default_prec = opt->precision;
     s->t0 = Clock::now();
+    if (!opt->independent) {
+        for (TickGroup *&g : s->group) {
+            g = tick_group_create(s->device);
+            if (!g) {
+                for (TickGroup *h : s->group) tick_group_destroy(h);
+                set_error("could not create the serving tick groups");
+                return nullptr;
+            }
+        }
+    }
     fdm_server *raw = s.get();
     for (int i = 0; i < s->max_active; ++i) s->workers.emplace_back(executor_loop, raw);
     s->admitter = std::thread(admission_loop, raw);
@@ -401,6 +424,7 @@ void fdm_server_destroy(fdm_server *s) {
     }
     for (auto &t : s->workers) t.join();
     s->admitter.join();
+    for (TickGroup *g : s->group) tick_group_destroy(g);
     // results nobody collected, and every pooled block
     s->pool.release_all();
     delete s;

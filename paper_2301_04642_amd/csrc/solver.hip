@@ -126,6 +126,7 @@ void Resources::view(const Layout &L, char *mem) {
 Resources::~Resources() {
     for (hipEvent_t e : ev)
         if (e) hipEventDestroy(e);
+    if (entry) hipEventDestroy(entry);
     for (hipEvent_t e : tev) hipEventDestroy(e);
     if (owned && base) hipFree(base);
     // the mapped host mirror is intentionally kept until process exit
@@ -138,6 +139,8 @@ int Resources::init(int dev) {
         e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
         if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
     }
+    e = hipEventCreateWithFlags(&entry, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
     e = hipHostMalloc((void **)&hm_host, sizeof(HostMirror),
                       hipHostMallocMapped | hipHostMallocCoherent);
     if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
@@ -308,6 +311,22 @@ int Ctx::product(int prec, const void *A, const void *B, const void *E, void *C,
     }
     last_ntiles = a.ntiles;
     used_tile = bt;
+    if (cap) {
+        // recorded for the serving tick (launched grouped with other solves)
+        StepOp o;
+        o.kind = StepOp::PRODUCT;
+        o.prec = prec;
+        o.bt = bt;
+        o.direct = symprod_direct(prec, bt, a.ld);
+        o.a = a;
+        cap->ops.push_back(std::move(o));
+        phase_launches.push_back(prec);
+        if (cap_stream) {
+            tick_post(group, &member, cap_seq++, std::move(stream_step));
+            stream_step.ops.clear();
+        }
+        return FDM_OK;
+    }
     hipError_t e;
     if (opt.timing) {
         hipEvent_t e0 = r->timing_event(2 * timed.size()), e1 = r->timing_event(2 * timed.size() + 1);
@@ -346,6 +365,13 @@ void Ctx::close_phase(int executed) {
 }
 
 int Ctx::decide(int mode, int count, int stride) {
+    if (cap) {
+        StepOp o;
+        o.kind = StepOp::DECIDE;
+        o.d = DecideJob{r->st, r->hm_dev, r->part, count, mode, stride, 0};
+        cap->ops.push_back(std::move(o));
+        return FDM_OK;
+    }
     hipError_t e = launch_decide(r->st, r->hm_dev, r->part, count, mode, stride, s);
     return e == hipSuccess ? FDM_OK : hip_fail(e, "decide launch");
 }
@@ -357,6 +383,32 @@ int Ctx::set_params(double tau, int max_iter, int switch_mode, int reset_all) {
 
 int Ctx::affine(int in_f32, const void *in, int64_t ldi, int out_f32, void *out, double a,
                 double b, int zt, int *nparts) {
+    if (cap) {
+        // recorded for the serving tick, with the companion split it implies
+        const int64_t ld = r->lay.ld, np = r->lay.np;
+        const int nn = (int)n;
+        const DevState *st = r->st;
+        double *part = r->part;
+        uint16_t *hl = nullptr;
+        if (out_f32 && (split_prec == P_F16X3 || split_prec == P_BF16X3)) {
+            const size_t m = (size_t)np * ld;
+            const float *f = (const float *)out;
+            if (f >= r->x32 && f < r->x32 + (size_t)r->lay.n32 * m)
+                hl = r->x16 + (size_t)(f - r->x32) / m * 2 * m;
+        }
+        const int sp = split_prec;
+        if (nparts) *nparts = affine_blocks((int)np);
+        StepOp o;
+        o.kind = StepOp::CUSTOM;
+        o.custom = [=](hipStream_t st_) -> hipError_t {
+            hipError_t e = launch_affine(in_f32, in, ldi, out_f32, out, ld, nn, (int)np, a, b, zt,
+                                         st, part, nullptr, st_);
+            if (e == hipSuccess && hl) e = launch_split(sp, (const float *)out, hl, ld, np, st_);
+            return e;
+        };
+        cap->ops.push_back(std::move(o));
+        return FDM_OK;
+    }
     hipError_t e = launch_affine(in_f32, in, ldi, out_f32, out, r->lay.ld, (int)n,
                                  (int)r->lay.np, a, b, zt, r->st, r->part, nparts, s);
     if (e != hipSuccess) return hip_fail(e, "affine launch");
@@ -401,7 +453,75 @@ static int lookahead() {
     return look;
 }
 
+// The same loop inside a serving tick group: the steps are recorded and
+// posted, the group launches them with other solves' steps, and the host
+// waits for each step's event as above.
+int Ctx::run_loop_grouped(int max_steps, const std::function<int(int)> &enqueue) {
+    const int every = progress_every();
+    const int look = lookahead();
+    volatile int32_t *done = &r->hm_host->done;
+    *done = 0;
+    int rc = tick_join(group, &member, s);
+    if (rc) return rc;
+    int issued = 0;
+    auto issue = [&]() -> int {
+        Step st;
+        cap = &st;
+        int q = enqueue(issued);
+        cap = nullptr;
+        if (q) return q;
+        tick_post(group, &member, issued, std::move(st));
+        ++issued;
+        return FDM_OK;
+    };
+    while (rc == FDM_OK && issued < max_steps && issued <= look) rc = issue();
+    for (int k = 0; rc == FDM_OK && k < max_steps; ++k) {
+        rc = tick_wait(group, &member, k);
+        if (rc) break;
+        if (every > 0 && (k + 1) % every == 0) {
+            fprintf(stderr, "[fdm] n=%lld step %d done\n", (long long)n, k + 1);
+            fflush(stderr);
+        }
+        if (*done) break;
+        if (issued < max_steps) rc = issue();
+    }
+    const int rc2 = tick_leave(group, &member);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    if (*done) return FDM_OK;
+    set_error("internal: phase ended without a device decision");
+    return FDM_EHIP;
+}
+
+// Finite-temperature evaluations inside a tick group: every launch of the
+// evaluation is recorded, and a step is posted at each product; the host
+// waits once, at the end.
+int Ctx::begin_stream_capture() {
+    if (!group) return FDM_OK;
+    int rc = tick_join(group, &member, s);
+    if (rc) return rc;
+    stream_step.ops.clear();
+    cap = &stream_step;
+    cap_stream = true;
+    cap_seq = 0;
+    return FDM_OK;
+}
+
+int Ctx::end_stream_capture() {
+    if (!group) return FDM_OK;
+    if (!stream_step.ops.empty()) {
+        tick_post(group, &member, cap_seq++, std::move(stream_step));
+        stream_step.ops.clear();
+    }
+    cap = nullptr;
+    cap_stream = false;
+    int rc = cap_seq > 0 ? tick_wait(group, &member, cap_seq - 1) : FDM_OK;
+    const int rc2 = tick_leave(group, &member);
+    return rc ? rc : rc2;
+}
+
 int Ctx::run_loop(int max_steps, const std::function<int(int)> &enqueue) {
+    if (group) return run_loop_grouped(max_steps, enqueue);
     const int every = progress_every();
     const int look = lookahead();
     // The device writes the mirror once, when it decides to stop; every step
@@ -1299,6 +1419,17 @@ const char *fdm_last_error(void) { return last_error(); }
 int fermi_dm_solve(const double *Hp, int64_t N, int64_t ldh, double n_occ, double kT, double tol,
                    double *D, int64_t ldd, double *E_band, const fdm_options *opt_in,
                    fdm_stats *stats_out, void *stream) {
+    return fdm::solve_impl(Hp, N, ldh, n_occ, kT, tol, D, ldd, E_band, opt_in, stats_out,
+                           (hipStream_t)stream, nullptr);
+}
+
+}  // extern "C"
+
+namespace fdm {
+
+int solve_impl(const double *Hp, int64_t N, int64_t ldh, double n_occ, double kT, double tol,
+               double *D, int64_t ldd, double *E_band, const fdm_options *opt_in,
+               fdm_stats *stats_out, hipStream_t stream, TickGroup *group) {
     const auto t0 = std::chrono::steady_clock::now();
     set_error("");
     fdm_options opt;
@@ -1334,12 +1465,18 @@ int fermi_dm_solve(const double *Hp, int64_t N, int64_t ldh, double n_occ, doubl
     if (!r) return FDM_EHIP;
     Ctx c;
     c.r = r;
-    c.s = (hipStream_t)stream;
+    c.s = stream;
     c.opt = opt;
     c.n = N;
     c.n_occ = n_occ;
     c.tol = tol;
     c.kT = kT;
+    if (group) {
+        c.group = group;
+        c.member.ev = r->ev;
+        c.member.entry = r->entry;
+        c.opt.timing = 0;
+    }
     memset(&c.stats, 0, sizeof(c.stats));
     c.stats.homo_ub = c.stats.lumo_lb = NAN;
     c.stats.lanczos_min = c.stats.lanczos_max = c.stats.cert_radius = NAN;
@@ -1358,12 +1495,18 @@ int fermi_dm_solve(const double *Hp, int64_t N, int64_t ldh, double n_occ, doubl
     }
     c.stats.status = rc;
     c.stats.tile = c.used_tile;
+    c.stats.tick_steps = c.member.steps;
+    c.stats.tick_shared = c.member.shared;
     c.stats.ms_total =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (stats_out) *stats_out = c.stats;
     if (rc == FDM_ENOCONV && fdm_last_error()[0] == 0) set_error("iteration cap or stagnation");
     return rc;
 }
+
+}  // namespace fdm
+
+extern "C" {
 
 int fdm_gershgorin(const double *H, int64_t N, int64_t ldh, double *out, int32_t *nonfinite,
                    void *stream) {

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <chrono>
+#include <deque>
 #include <functional>
 #include <vector>
 
@@ -33,6 +34,8 @@ Layout plan_product_layout(int64_t n, int prec);
 // Events of the steps in flight (one ring per host thread and device).
 constexpr int kEvRing = 8;
 
+struct TickGroup;
+
 // Per host thread and device: the cached workspace, the mapped host mirror
 // of the device state, and events.
 struct Resources {
@@ -54,6 +57,7 @@ struct Resources {
     DevState *st_pinned = nullptr;
     DevState st_fallback;
     hipEvent_t ev[kEvRing] = {};
+    hipEvent_t entry = nullptr;  // joins a tick group (serving)
     std::vector<hipEvent_t> tev;
 
     ~Resources();
@@ -71,6 +75,12 @@ int sym_product_bound(Resources *r, int32_t precision, const double *A, const do
                       const double *E, double *C, int64_t N, int64_t ld, double alpha,
                       double beta, double gamma, double *sums, int32_t tile, hipStream_t s);
 
+// fermi_dm_solve with an optional serving tick group (the server's
+// executors pass theirs; group == nullptr launches on `stream` directly).
+int solve_impl(const double *Hp, int64_t N, int64_t ldh, double n_occ, double kT, double tol,
+               double *D, int64_t ldd, double *E_band, const fdm_options *opt_in,
+               fdm_stats *stats_out, hipStream_t stream, TickGroup *group);
+
 int hip_fail(hipError_t e, const char *what);
 const char *last_error();
 
@@ -79,6 +89,49 @@ struct Timed {
     size_t e0, e1;
     bool real;
 };
+
+// ---- serving tick (tick.cpp) -----------------------------------------------
+// One step of a solve's hot loop as recorded for a tick group instead of
+// launched: products, decisions and other launches, in order.
+struct StepOp {
+    enum Kind { PRODUCT, DECIDE, CUSTOM } kind;
+    int prec = 0, bt = 0;
+    bool direct = false;
+    ProdArgs a;
+    DecideJob d;
+    std::function<hipError_t(hipStream_t)> custom;
+};
+struct Step {
+    std::vector<StepOp> ops;
+};
+
+// A solve taking part in a tick group (one per solve context).
+struct TickMember {
+    hipEvent_t *ev = nullptr;    // ring of kEvRing events: ev[seq % kEvRing] follows step seq
+    hipEvent_t entry = nullptr;  // recorded on the member's stream when it joins
+    bool entered = false;        // the group stream already waits on `entry`
+    std::deque<std::pair<int, Step>> posted;  // steps not yet launched, in order
+    int launched = -1;           // last step launched
+    int taken = 0;               // steps the ticker is launching right now
+    int error = 0;
+    int steps = 0, shared = 0;   // steps launched; of them, in a tick with another solve's
+};
+
+// Runs the hot-loop steps of several solves together: each tick takes the
+// next posted step of every member and launches their products as grouped
+// products (one launch per precision, tile edge and staging path) and their
+// decisions as one grouped decision, on the group's own stream.
+struct TickGroup;
+TickGroup *tick_group_create(int device);
+void tick_group_destroy(TickGroup *g);
+// Joins g: the group stream will wait for everything enqueued on s so far.
+int tick_join(TickGroup *g, TickMember *m, hipStream_t s);
+void tick_post(TickGroup *g, TickMember *m, int seq, Step &&st);
+// Waits until step seq has run on the device.
+int tick_wait(TickGroup *g, TickMember *m, int seq);
+// Drops the member's unlaunched steps, waits for its launched ones to finish
+// and leaves the group.
+int tick_leave(TickGroup *g, TickMember *m);
 
 // One call's context.
 struct Ctx {
@@ -102,6 +155,16 @@ struct Ctx {
     std::vector<double> az_gap;  // h - l before the first and after each accelerated step
     std::vector<Timed> timed;
     std::chrono::steady_clock::time_point tmark = std::chrono::steady_clock::now();
+    // serving tick: when group is set, the hot loops' launches are recorded
+    // into *cap (a step) and run by the group instead of on s
+    TickGroup *group = nullptr;
+    TickMember member;
+    Step *cap = nullptr;
+    Step stream_step;          // the step being recorded in stream capture
+    bool cap_stream = false;   // post a step at every product (finite-T evaluations)
+    int cap_seq = 0;
+    int begin_stream_capture();
+    int end_stream_capture();
 
     int tile_for(int prec) const;
     int product(int prec, const void *A, const void *B, const void *E, void *C, const double c0[3],
@@ -112,6 +175,7 @@ struct Ctx {
     int affine(int in_f32, const void *in, int64_t ldi, int out_f32, void *out, double a,
                double b, int zt, int *nparts);
     int run_loop(int max_steps, const std::function<int(int)> &enqueue);
+    int run_loop_grouped(int max_steps, const std::function<int(int)> &enqueue);
     int sp2_phase(int prec, void *b0, void *b1, int max_iter, int switch_mode, double tau,
                   int sched_off, void **result, int *iters);
     void build_az_schedule(double l0, double h0, int steps);

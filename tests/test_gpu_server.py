@@ -24,7 +24,8 @@ def requests(count=10):
     return [(r, workloads.serving_workload(r)) for r in reqs]
 
 
-def test_alone_equals_mix(fdm):
+@pytest.mark.parametrize("grouped", [True, False])
+def test_alone_equals_mix(fdm, grouped):
     reqs = requests(10)
     prec = "fp32"
     alone = {}
@@ -32,7 +33,8 @@ def test_alone_equals_mix(fdm):
         say("alone", r["id"], wl.n)
         D, e, st = fdm.solve(dev(wl.hp), wl.n_occ, wl.kT, 1e-8, prec)
         alone[r["id"]] = (host(D), e)
-    srv = fdm.Server(budget_bytes=8 << 30, max_active=4, precision=prec)
+    srv = fdm.Server(budget_bytes=8 << 30, max_active=4, precision=prec, grouped=grouped)
+    shared = 0
     try:
         tickets = {}
         t0 = time.time()
@@ -53,12 +55,90 @@ def test_alone_equals_mix(fdm):
             assert abs(e - e_ref) <= 1e-6
             starts.append(times[1])
             finishes.append(times[2])
+            shared += st.tick_shared
+            if grouped:
+                assert st.tick_steps > 0
+            else:
+                assert st.tick_steps == 0
         # work overlapped: some request started before another had finished
         order = np.argsort(starts)
         overlapped = any(starts[order[i + 1]] < finishes[order[i]] for i in range(len(order) - 1))
         assert overlapped
+        if grouped:
+            # on the device: steps of different requests ran in the same
+            # grouped product and decision launches
+            print(f"[report] grouped ticks: {shared} shared steps", flush=True)
+            assert shared > 0
     finally:
         srv.close()
+
+
+def test_alone_equals_mix_wide(fdm):
+    """A mix up to N ~ 4000 (log-uniform 500 ... 4000), half finite
+    temperature, precisions FP32 / FP16x3 / BF16x3 per request: each served
+    result is bitwise the solve alone."""
+    reqs = [(r, workloads.serving_workload(r))
+            for r in workloads.serving_requests(8, n_lo=500, n_hi=4000, rate=100.0, seed=77)]
+    precs = ["fp32", "fp16x3", "bf16x3"]
+    alone = {}
+    for k, (r, wl) in enumerate(reqs):
+        say("alone wide", r["id"], wl.n, wl.kT, precs[k % 3])
+        D, e, st = fdm.solve(dev(wl.hp), wl.n_occ, wl.kT, 1e-8, precs[k % 3])
+        alone[r["id"]] = (host(D), e)
+    srv = fdm.Server(budget_bytes=40 << 30, max_active=4, precision="fp32")
+    try:
+        tickets = {r["id"]: srv.submit(wl.hp, wl.n_occ, wl.kT, 1e-8, precision=precs[k % 3])
+                   for k, (r, wl) in enumerate(reqs)}
+        shared = 0
+        for r, wl in reqs:
+            say("mix wide result", r["id"])
+            rc, d, e, st, times = srv.result(tickets[r["id"]], wl.n)
+            assert rc == 0
+            assert np.array_equal(d, alone[r["id"]][0]), r["id"]
+            assert e == alone[r["id"]][1]
+            shared += st.tick_shared
+        print(f"[report] wide mix: {shared} shared steps", flush=True)
+        assert shared > 0
+    finally:
+        srv.close()
+
+
+def test_held_memory_within_budget(fdm):
+    """Device blocks held by the server (in use or pooled) never exceed the
+    budget over a log-uniform mix of sizes."""
+    reqs = [(r, workloads.serving_workload(r))
+            for r in workloads.serving_requests(12, n_lo=200, n_hi=2500, rate=100.0, seed=78)]
+    budget = 1 << 30
+    srv = fdm.Server(budget_bytes=budget, max_active=4, precision="fp32")
+    try:
+        tickets = [(srv.submit(wl.hp, wl.n_occ, wl.kT, 1e-8), wl) for r, wl in reqs]
+        peak = 0
+        for t, wl in tickets:
+            say("budget mix", wl.n)
+            rc, d, e, st, times = srv.result(t, wl.n)
+            assert rc == 0
+            held, reserved, pooled = srv.memory()
+            peak = max(peak, held)
+            assert held <= budget and reserved <= budget
+        print(f"[report] budget {budget >> 20} MiB: peak held {peak >> 20} MiB", flush=True)
+    finally:
+        srv.close()
+
+
+def test_destroy_with_uncollected_results(fdm):
+    """Closing a server whose budget fits one request at a time, with results
+    nobody collected and requests that never started, returns."""
+    n = 300
+    foot = fdm.fdm_workspace_bytes(n, 0.0, fdm.FDM_FP32) + 2 * n * n * 8
+    srv = fdm.Server(budget_bytes=foot + foot // 2, max_active=2, precision="fp32")
+    wls = [workloads.standard_workload("gapped", n=n, seed_base=90 + i) for i in range(4)]
+    ts = [srv.submit(w.hp, w.n_occ, 0.0, 1e-8) for w in wls]
+    say("destroy: wait for the first result")
+    while srv.poll(ts[0]) == 1:
+        time.sleep(0.001)
+    t0 = time.time()
+    srv.close()
+    assert time.time() - t0 < 30.0
 
 
 def test_budget_enforced(fdm):

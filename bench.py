@@ -17,8 +17,9 @@ given the HOMO/LUMO bounds an earlier solve estimated) is listed under
 (skipped with --no-legs): "latency_n256", the single N = 256 FP64 solve in
 microseconds, and "serving", the continuous-batching server on 32 requests
 with N log-uniform in [500, 16000] (half gapped at kT = 0, half metallic at
-kT = 0.0016 Ha), FP32 and BF16x3, closed loop and then Poisson arrivals at
-0.8 x capacity (p50 / p99 latency), against one-at-a-time FP64 solves.
+kT = 0.0016 Ha), FP32 and BF16x3 with grouped ticks and FP32 with each
+request on its own stream, closed loop and then Poisson arrivals at 0.8 x
+capacity (p50 / p99 latency), against one-at-a-time FP64 solves.
 """
 import argparse
 import json
@@ -190,6 +191,9 @@ def latency_leg(fdm, torch, solves=200):
 
 
 def serving(args, precisions=None, log_every=8):
+    """precisions: served forms, each a precision name, optionally suffixed
+    "+independent" (each request on its own stream instead of grouped
+    ticks)."""
     """Continuous-batching server under Poisson arrivals: closed-loop
     capacity, then an open loop at args.load x capacity (p50/p99 latency,
     solves/s), for each served precision, against one-at-a-time FP64 solves
@@ -229,9 +233,11 @@ def serving(args, precisions=None, log_every=8):
     budget = int(args.budget_gb * (1 << 30))
     arrival_rng = np.random.default_rng(4_999_998)
 
-    def run(arrivals, prec):
+    def run(arrivals, form):
+        prec, *mods = form.split("+")
+        grouped = not (args.serve_independent or "independent" in mods)
         srv = fdm.Server(budget_bytes=budget, max_active=args.max_active, precision=prec,
-                         grouped=not args.serve_independent)
+                         grouped=grouped)
         t0 = time.perf_counter()
         tickets = []
         for q, at in zip(reqs, arrivals):
@@ -449,7 +455,7 @@ def main():
         log("compact serving leg")
         leg = argparse.Namespace(**vars(args))
         leg.requests, leg.n_min, leg.n_max = args.leg_requests, 500, 16000
-        out["serving"] = serving(leg, precisions=["fp32", "bf16x3"])
+        out["serving"] = serving(leg, precisions=["fp32", "bf16x3", "fp32+independent"])
     if not args.no_cpu:
         # the oracle runs its own plain FP64 SP2 with Gershgorin bounds; the
         # fp64 form's product count only sizes a partial run at large N

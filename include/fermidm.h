@@ -79,7 +79,7 @@ typedef struct fdm_options {
     int32_t fd_final_fp64;  /* finite T, low precision: finish with one FP64 evaluation (1)    */
     int32_t validate;       /* 1: reject an Hp that is not symmetric to 1e-12 relative (0)     */
     int32_t timing;         /* 1: time every product launch with HIP events (0)                */
-    int32_t tile;           /* product tile edge: 0 = automatic, or 64 / 128                   */
+    int32_t tile;           /* product tile edge: 0 = automatic, or 32 (N <= 2048) / 64 / 128   */
     int32_t bounds;         /* spectral bounds (Sec. II.C): 0 = Gershgorin discs; 1 (default)
                                = a Lanczos estimate of the extreme eigenvalues (Ritz values
                                widened by their residual bounds and 1% of the width), interval
@@ -261,7 +261,7 @@ int fdm_gershgorin(const double *H, int64_t N, int64_t ldh, double *out, int32_t
  *  A, B, E  device, N x N float64, leading dimension ld (E nullable = 0).
  *  C        device, N x N float64, leading dimension ld; may not alias A/B/E.
  *  sums     host double[3] (nullable): Tr C, ||C||_F^2, ||A B - E||_F^2.
- *  tile     0 = automatic, or 64 / 128.
+ *  tile     0 = automatic, or 32 (N <= 2048; 64 above) / 64 / 128.
  * A and B are expected to commute (for X^2, A == B); only their product's
  * upper triangle is formed.
  */

@@ -25,9 +25,20 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 // Product tiles are listed in bands of this many tile rows (see upper_tiles).
 constexpr int kTileBand = 8;
+// 32-wide tiles exist (and their list is kept) only up to this size.
+constexpr int64_t kTile32MaxN = 2048;
 
-// Tile edge (64 or 128) of a product of size n in precision prec; forced = 64
-// or 128 overrides the measured choice.
+// Tile rows (and columns) of a product of size n with bt-wide tiles.  The
+// tiles cover at least the K extent round_up(n, kKStep) that the products
+// read: the working matrices' padding is zero only where a kernel wrote
+// zeros, and a product writes exactly its tiles, so 32-wide tiles add a
+// row and column of padding tiles when ceil(n / 32) is odd.
+inline int64_t tile_rows(int64_t n, int bt) {
+    return bt == 32 ? (n + 63) / 64 * 2 : (n + bt - 1) / bt;
+}
+
+// Tile edge (32, 64 or 128) of a product of size n in precision prec; forced
+// = 32 (n <= kTile32MaxN), 64 or 128 overrides the measured choice.
 int choose_tile(int64_t n, int prec, int forced);
 
 // Decide-kernel modes (what the partial sums of the preceding launch mean).

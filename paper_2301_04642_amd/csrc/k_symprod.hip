@@ -12,6 +12,7 @@
 //
 // CDNA4 mapping:
 //  * 256 threads = 4 wave64s in a 2 x 2 arrangement; a block owns a BT x BT
+//    (BT = 32, 64 or 128)
 //    output tile, each wave a (BT/2)^2 sub-tile of 16 x 16 MFMA blocks.
 //  * Both operands are read as row panels of the row-major matrices: rows
 //    ti*BT.. of A and rows tj*BT.. of B (B symmetric, so B[k][j] = B[j][k]),
@@ -339,7 +340,7 @@ __device__ __forceinline__ void symprod_tile(const ProdArgs &a, const int t) {
     //    tau.
     //  * Single-pass 16-bit forms: compensated fold of every stage on 64-wide
     //    tiles, direct accumulation on 128-wide ones.
-    constexpr bool KAHAN = (P != P_F64 && P != P_F32 && !SPLIT) && BT == 64;
+    constexpr bool KAHAN = (P != P_F64 && P != P_F32 && !SPLIT) && BT <= 64;
     constexpr bool TWOLEVEL = (P == P_F32) || SPLIT;
     constexpr bool COMP = KAHAN || TWOLEVEL;
     constexpr int FOLD = SPLIT ? 8 : (TWOLEVEL ? 4 : 1);
@@ -565,14 +566,15 @@ __device__ __forceinline__ void symprod_tile(const ProdArgs &a, const int t) {
     }
 }
 
-// 64-wide tiles are register-capped to four waves per SIMD (four blocks per
-// CU); 128-wide FP64, FP32 and split tiles to two (two blocks per CU: 64 x 64
+// 32-wide tiles (small products: more blocks) run up to eight waves per
+// SIMD; 64-wide tiles are register-capped to four waves per SIMD (four
+// blocks per CU); 128-wide FP64, FP32 and split tiles to two (two blocks per CU: 64 x 64
 // outputs per wave, half the panel and LDS fragment traffic per flop of a
 // 64-wide tile); the single-pass 16-bit 128-wide tiles run one wave per SIMD.
 #define FDM_SYMPROD_ATTRS(P, BT)                                                        \
     __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(                          \
-        BT == 64 ? 4 : ((P == P_F32 || P == P_F64 || PT<P>::SPLIT) ? 2 : 1),             \
-        BT == 64 ? 4 : ((P == P_F32 || P == P_F64 || PT<P>::SPLIT) ? 2 : 1))))
+        BT == 32 ? 8 : BT == 64 ? 4 : ((P == P_F32 || P == P_F64 || PT<P>::SPLIT) ? 2 : 1), \
+        BT == 32 ? 8 : BT == 64 ? 4 : ((P == P_F32 || P == P_F64 || PT<P>::SPLIT) ? 2 : 1))))
 
 template <int P, int BT, bool DMA>
 __global__ FDM_SYMPROD_ATTRS(P, BT) void k_symprod(ProdArgs a) {
@@ -609,8 +611,8 @@ constexpr int64_t kSplitDirectMaxLd = 18432;
 
 template <int P, int BT>
 bool direct_t(int64_t ld) {
-    if constexpr (PT<P>::SPLIT) return (BT == 64) || ld <= kSplitDirectMaxLd;
-    else if constexpr (P == P_F64 || P == P_F32) return BT == 128;
+    if constexpr (PT<P>::SPLIT) return (BT <= 64) || ld <= kSplitDirectMaxLd;
+    else if constexpr (P == P_F64 || P == P_F32) return BT != 64;
     return false;
 }
 
@@ -627,6 +629,7 @@ hipError_t launch_t(const ProdArgs &a, hipStream_t s) {
 template <int P>
 hipError_t launch_p(int bt, const ProdArgs &a, hipStream_t s) {
     if (bt == 128) return launch_t<P, 128>(a, s);
+    if (bt == 32) return launch_t<P, 32>(a, s);
     return launch_t<P, 64>(a, s);
 }
 
@@ -643,6 +646,7 @@ hipError_t launch_grouped_t(bool direct, const ProdGroup &g, int total, hipStrea
 template <int P>
 hipError_t launch_grouped_p(int bt, bool direct, const ProdGroup &g, int total, hipStream_t s) {
     if (bt == 128) return launch_grouped_t<P, 128>(direct, g, total, s);
+    if (bt == 32) return launch_grouped_t<P, 32>(direct, g, total, s);
     return launch_grouped_t<P, 64>(direct, g, total, s);
 }
 
@@ -650,11 +654,18 @@ hipError_t launch_grouped_p(int bt, bool direct, const ProdGroup &g, int total, 
 
 bool symprod_direct(int prec, int bt, int64_t ld) {
     switch (prec) {
-        case P_F64: return bt == 128 ? direct_t<P_F64, 128>(ld) : direct_t<P_F64, 64>(ld);
-        case P_F32: return bt == 128 ? direct_t<P_F32, 128>(ld) : direct_t<P_F32, 64>(ld);
-        case P_F16X3: return bt == 128 ? direct_t<P_F16X3, 128>(ld) : direct_t<P_F16X3, 64>(ld);
+        case P_F64:
+            return bt == 128 ? direct_t<P_F64, 128>(ld)
+                             : (bt == 32 ? direct_t<P_F64, 32>(ld) : direct_t<P_F64, 64>(ld));
+        case P_F32:
+            return bt == 128 ? direct_t<P_F32, 128>(ld)
+                             : (bt == 32 ? direct_t<P_F32, 32>(ld) : direct_t<P_F32, 64>(ld));
+        case P_F16X3:
+            return bt == 128 ? direct_t<P_F16X3, 128>(ld)
+                             : (bt == 32 ? direct_t<P_F16X3, 32>(ld) : direct_t<P_F16X3, 64>(ld));
         case P_BF16X3:
-            return bt == 128 ? direct_t<P_BF16X3, 128>(ld) : direct_t<P_BF16X3, 64>(ld);
+            return bt == 128 ? direct_t<P_BF16X3, 128>(ld)
+                             : (bt == 32 ? direct_t<P_BF16X3, 32>(ld) : direct_t<P_BF16X3, 64>(ld));
         default: return false;
     }
 }

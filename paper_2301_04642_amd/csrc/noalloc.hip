@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_zero16(uint4 *p, size_t words) {
 
 // The upper-triangular tile list (ti <= tj) in the same banded order as the
 // host-built lists of the cached workspace: bands of kTileBand tile rows,
-// each walked column by column.  One thread; nt <= 1408 / 64 = 22 here.
+// each walked column by column.  One thread; nt <= 1408 / 32 = 44 here.
 __global__ void k_upper_tiles(uint32_t *out, int nt) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     int k = 0;
@@ -107,8 +107,9 @@ int fdm_sym_product_noalloc(int32_t precision, const double *A, const double *B,
     const size_t words = L.bytes / 16;
     const int blocks = (int)std::min<size_t>((words + 255) / 256, 2048);
     hipLaunchKernelGGL(k_zero16, dim3(blocks), dim3(256), 0, s, (uint4 *)mem, words);
-    hipLaunchKernelGGL(k_upper_tiles, dim3(1), dim3(1), 0, s, r.tiles64, (int)((N + 63) / 64));
-    hipLaunchKernelGGL(k_upper_tiles, dim3(1), dim3(1), 0, s, r.tiles128, (int)((N + 127) / 128));
+    hipLaunchKernelGGL(k_upper_tiles, dim3(1), dim3(1), 0, s, r.tiles64, (int)tile_rows(N, 64));
+    hipLaunchKernelGGL(k_upper_tiles, dim3(1), dim3(1), 0, s, r.tiles128, (int)tile_rows(N, 128));
+    hipLaunchKernelGGL(k_upper_tiles, dim3(1), dim3(1), 0, s, r.tiles32, (int)tile_rows(N, 32));
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "scratch set-up launch");
     return sym_product_bound(&r, precision, A, B, E, C, N, ld, alpha, beta, gamma, sums, tile, s);

@@ -57,7 +57,7 @@ static std::vector<uint32_t> upper_tiles(int nt) {
 }
 
 static int64_t ntiles_for(int64_t n, int bt) {
-    const int64_t nt = (n + bt - 1) / bt;
+    const int64_t nt = tile_rows(n, bt);
     return nt * (nt + 1) / 2;
 }
 
@@ -76,7 +76,8 @@ static Layout plan_mats(int64_t n, int n64, int n32) {
     L.n32 = n32;
     const size_t mat64 = (size_t)L.np * L.ld * 8, mat32 = (size_t)L.np * L.ld * 4;
     const int64_t tiles64 = ntiles_for(n, 64), tiles128 = ntiles_for(n, 128);
-    const int64_t parts = std::max<int64_t>({tiles64, (L.np + 3) / 4, 1});
+    const int64_t tiles32 = n <= kTile32MaxN ? ntiles_for(n, 32) : 0;
+    const int64_t parts = std::max<int64_t>({tiles32, tiles64, (L.np + 3) / 4, 1});
     size_t off = 0;
     L.off64 = off;
     off += mat64 * L.n64;
@@ -90,6 +91,8 @@ static Layout plan_mats(int64_t n, int n64, int n32) {
     off += round_up(tiles64 * 4, 256);
     L.off_tiles128 = off;
     off += round_up(tiles128 * 4, 256);
+    L.off_tiles32 = off;
+    off += round_up(std::max<int64_t>(tiles32, 1) * 4, 256);
     L.off_lanczos = off;
     off += round_up((5 * L.np + 2 * kMaxLanczos) * sizeof(double), 256);
     L.off_state = off;
@@ -97,6 +100,7 @@ static Layout plan_mats(int64_t n, int n64, int n32) {
     L.bytes = off;
     L.ntiles64 = (int)tiles64;
     L.ntiles128 = (int)tiles128;
+    L.ntiles32 = (int)tiles32;
     L.part_cap = parts;
     return L;
 }
@@ -119,6 +123,7 @@ void Resources::view(const Layout &L, char *mem) {
     part = (double *)(mem + L.off_part);
     tiles64 = (uint32_t *)(mem + L.off_tiles64);
     tiles128 = (uint32_t *)(mem + L.off_tiles128);
+    tiles32 = (uint32_t *)(mem + L.off_tiles32);
     st = (DevState *)(mem + L.off_state);
     lanczos = (double *)(mem + L.off_lanczos);
 }
@@ -197,12 +202,18 @@ int Resources::bind(const Layout &L, void *user_mem, size_t user_bytes, hipStrea
         if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
         e = hipMemsetAsync(st, 0, sizeof(DevState), s);
         if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
-        std::vector<uint32_t> t64 = upper_tiles((int)((L.n + 63) / 64));
-        std::vector<uint32_t> t128 = upper_tiles((int)((L.n + 127) / 128));
+        std::vector<uint32_t> t64 = upper_tiles((int)tile_rows(L.n, 64));
+        std::vector<uint32_t> t128 = upper_tiles((int)tile_rows(L.n, 128));
         e = hipMemcpyAsync(tiles64, t64.data(), t64.size() * 4, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
         e = hipMemcpyAsync(tiles128, t128.data(), t128.size() * 4, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+        std::vector<uint32_t> t32;
+        if (L.ntiles32 > 0) {
+            t32 = upper_tiles((int)tile_rows(L.n, 32));
+            e = hipMemcpyAsync(tiles32, t32.data(), t32.size() * 4, hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+        }
         e = hipStreamSynchronize(s);  // the host vectors die here
         if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
         bound_mem = mem;
@@ -241,6 +252,11 @@ int Ctx::tile_for(int prec) const { return choose_tile(n, prec, opt.tile); }
 
 int choose_tile(int64_t n, int prec, int forced) {
     if (forced == 64 || forced == 128) return forced;
+    if (forced == 32) return n <= kTile32MaxN ? 32 : 64;
+    // Small products: fewer than 128 tiles of 64 leave most of the 256 CUs
+    // idle, and a product is launch- and latency-bound; 32-wide tiles give
+    // four times the blocks (N = 256: 36 instead of 10).
+    if (n <= kTile32MaxN && ntiles_for(n, 64) < 128) return 32;
     // Measured on MI355X.
     // FP32: 128-wide tiles (two waves per SIMD) once there are at least 16
     // waves of them for the chip (N >= ~11500): 108 -> 128 TFLOP/s on a
@@ -284,8 +300,8 @@ int Ctx::product(int prec, const void *A, const void *B, const void *E, void *C,
     a.ld = r->lay.ld;
     a.n = (int32_t)n;
     a.kext = (int32_t)round_up(n, kKStep);
-    a.tiles = (bt == 128) ? r->tiles128 : r->tiles64;
-    a.ntiles = (bt == 128) ? r->lay.ntiles128 : r->lay.ntiles64;
+    a.tiles = (bt == 128) ? r->tiles128 : (bt == 32 ? r->tiles32 : r->tiles64);
+    a.ntiles = (bt == 128) ? r->lay.ntiles128 : (bt == 32 ? r->lay.ntiles32 : r->lay.ntiles64);
     for (int k = 0; k < 3; ++k) {
         a.coef[0][k] = c0[k];
         a.coef[1][k] = c1 ? c1[k] : c0[k];
@@ -918,8 +934,8 @@ int Ctx::certify_bounds(const double *Hp, int64_t ldh, DevState *h) {
         a.ld = r->lay.ld;
         a.n = (int32_t)n;
         a.kext = (int32_t)round_up(n, kKStep);
-        a.tiles = (bt == 128) ? r->tiles128 : r->tiles64;
-        a.ntiles = (bt == 128) ? r->lay.ntiles128 : r->lay.ntiles64;
+        a.tiles = (bt == 128) ? r->tiles128 : (bt == 32 ? r->tiles32 : r->tiles64);
+        a.ntiles = (bt == 128) ? r->lay.ntiles128 : (bt == 32 ? r->lay.ntiles32 : r->lay.ntiles64);
         a.coef[0][0] = a.coef[1][0] = 1.0;
         a.partials = r->part;
         e = launch_symprod(P_F16X3, bt, a, s);
@@ -1304,7 +1320,8 @@ namespace fdm {
 bool sym_product_args_ok(int32_t precision, const double *A, const double *B, const double *E,
                          const double *C, int64_t N, int64_t ld, int32_t tile) {
     return A && B && C && N > 0 && ld >= N && N < 65535 * 64 && precision >= 0 &&
-           precision < FDM_NPREC && (tile == 0 || tile == 64 || tile == 128) && C != A &&
+           precision < FDM_NPREC && (tile == 0 || tile == 32 || tile == 64 || tile == 128) &&
+           C != A &&
            C != B && !(E && C == E);
 }
 
@@ -1439,7 +1456,8 @@ int solve_impl(const double *Hp, int64_t N, int64_t ldh, double n_occ, double kT
         fdm_options_default(&opt);
     if (!Hp || !D || N <= 0 || N >= 65535 * 64 || ldh < N || ldd < N || !(tol > 0.0) ||
         !(kT >= 0.0) || !std::isfinite(kT) || opt.precision < 0 || opt.precision >= FDM_NPREC ||
-        opt.max_iter <= 0 || (opt.tile != 0 && opt.tile != 64 && opt.tile != 128) ||
+        opt.max_iter <= 0 ||
+        (opt.tile != 0 && opt.tile != 32 && opt.tile != 64 && opt.tile != 128) ||
         opt.bounds < 0 || opt.bounds > 1 || opt.trfoe_depth < 0 ||
         (opt.reltr_schedule && !(opt.reltr_switch > 0.0 && opt.reltr_stop > 0.0))) {
         set_error("invalid argument");

@@ -22,10 +22,11 @@ struct Layout {
     int64_t n = 0, np = 0, ld = 0;
     int n64 = 0, n32 = 0;
     size_t off64 = 0, off32 = 0, off_part = 0, off_tiles64 = 0, off_tiles128 = 0, off_state = 0;
+    size_t off_tiles32 = 0;  // 32-wide tile list (small N only, else empty)
     size_t off_lanczos = 0;  // 5 vectors of np doubles + alpha/beta (2 x kMaxLanczos)
     size_t off16 = 0;        // hi/lo 16-bit companions of the FP32 buffers
     size_t bytes = 0;
-    int ntiles64 = 0, ntiles128 = 0;
+    int ntiles64 = 0, ntiles128 = 0, ntiles32 = 0;
     int64_t part_cap = 0;
 };
 Layout plan_layout(int64_t n, bool finite, int prec);
@@ -50,7 +51,7 @@ struct Resources {
     float *x32 = nullptr;
     uint16_t *x16 = nullptr;
     double *part = nullptr;
-    uint32_t *tiles64 = nullptr, *tiles128 = nullptr;
+    uint32_t *tiles64 = nullptr, *tiles128 = nullptr, *tiles32 = nullptr;
     double *lanczos = nullptr;
     DevState *st = nullptr;
     HostMirror *hm_host = nullptr, *hm_dev = nullptr;

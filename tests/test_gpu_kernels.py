@@ -75,7 +75,7 @@ def product_tol(prec, a, b):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x3", "bf16x3", "bf16", "fp16"])
 @pytest.mark.parametrize("n", [1, 63, 65, 257, 1000])
-@pytest.mark.parametrize("tile", [64, 128])
+@pytest.mark.parametrize("tile", [32, 64, 128])
 def test_square_sp2_epilogues(fdm, prec, n, tile):
     """X^2 and 2X - X^2 with the partial sums, against the FP64 definition."""
     import torch

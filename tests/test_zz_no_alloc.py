@@ -39,7 +39,7 @@ def _pair(fdm, prec, n, seed, tile):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x3", "bf16x3"])
-@pytest.mark.parametrize("tile", [0, 128])
+@pytest.mark.parametrize("tile", [0, 32, 128])
 def test_noalloc_matches_product_twice(fdm, prec, tile):
     _pair(fdm, prec, 1408, 11, tile)   # the largest size the array holds
     _pair(fdm, prec, 333, 12, tile)    # then a smaller, ragged one

@@ -13,9 +13,10 @@ plain FP64 SP2; every measured form (fp64, fp32, fp16x3, bf16x3, with
 Gershgorin or Lanczos-tightened bounds, and the accelerated expansion "+az"
 given the HOMO/LUMO bounds an earlier solve estimated) is listed under
 "forms", each with the Sec. III.C metrics of its last solve (eps1, eps2,
-||D - D_ref||_F, |Tr D - n_occ|, idempotency, RelTr).  Two extra legs follow
+||D - D_ref||_F, |Tr D - n_occ|, idempotency, RelTr).  Three extra legs follow
 (skipped with --no-legs): "latency_n256", the single N = 256 FP64 solve in
-microseconds, and "serving", the continuous-batching server on 32 requests
+microseconds; "large_n30000", one FP32-mixed and one FP64 solve of the
+N = 30000 band workload with 1% outliers up to 5 Ha; and "serving", the continuous-batching server on 32 requests
 with N log-uniform in [500, 16000] (half gapped at kT = 0, half metallic at
 kT = 0.0016 Ha), FP32 and BF16x3 with grouped ticks and FP32 with each
 request on its own stream, closed loop and then Poisson arrivals at 0.8 x
@@ -188,6 +189,48 @@ def latency_leg(fdm, torch, solves=200):
         log(f"latency n=256 fp64 {name}: {out[name]['us_per_solve']} us/solve "
             f"||dD||={q['D_minus_Dref_F']:.1e}")
     return dict(workload="gapped-n256-nocc64-gap0.2", precision="fp64", solves=solves, **out)
+
+
+def large_leg(fdm, torch):
+    """The large single solve: N = 30000, n_occ = 7500, the 20-band spectrum
+    with 1% outliers up to 5 Ha and a 0.05 Ha gap; FP32 mixed (certified
+    bounds) and plain FP64, one timed solve each after one FP32 warm-up."""
+    import numpy as np
+    import workloads
+    log("large leg: generating the N = 30000 workload")
+    wl = workloads.standard_workload("outliers")
+    e_ref = float(np.sort(wl.lam)[: int(wl.n_occ)].sum())
+    H = torch.from_numpy(wl.hp).cuda()
+    del wl.hp
+    D = torch.empty_like(H)
+    out = {"workload": "bands-outliers-n30000-nocc7500-gap0.05-tol1e-8"}
+    opt = fdm.fdm_options_default()
+    opt.precision = fdm.PRECISIONS["fp32"]
+    fdm.fermi_dm_solve(H, wl.n_occ, 0.0, 1e-8, D, opt)
+    for prec in ("fp32", "fp64"):
+        opt.precision = fdm.PRECISIONS[prec]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, e, st = fdm.fermi_dm_solve(H, wl.n_occ, 0.0, 1e-8, D, opt)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tr = float(D.diagonal().sum())
+        out[prec] = dict(seconds_per_solve=round(dt, 3), solves_per_s=round(1.0 / dt, 4),
+                         products={fdm.PREC_NAMES[p]: st.products[p] for p in range(fdm.FDM_NPREC)
+                                   if st.products[p]},
+                         abs_dE_Ha=float(f"{abs(e - e_ref):.3e}"),
+                         eps2=float(f"{(e - e_ref) / e_ref:.3e}"),
+                         trace_err=float(f"{abs(tr - wl.n_occ):.3e}"),
+                         idempotency=float(f"{st.idempotency:.3e}"),
+                         bounds=[round(st.e_min, 4), round(st.e_max, 4)],
+                         gate_pass=bool(rc == 0 and abs(e - e_ref) <= 1e-6 and
+                                        st.idempotency <= 1e-8))
+        log(f"large leg {prec}: {dt:.2f} s |dE|={abs(e - e_ref):.1e}")
+    out["speedup_fp32_vs_fp64"] = round(out["fp64"]["seconds_per_solve"] /
+                                        out["fp32"]["seconds_per_solve"], 3)
+    del H, D
+    torch.cuda.empty_cache()
+    return out
 
 
 def serving(args, precisions=None, log_every=8):
@@ -447,11 +490,13 @@ def main():
         "forms": forms_out,
         "extra_keys_note": "forms: every measured form with its quality_last_solve (Sec. III.C "
                            "eps1, eps2 and the absolute gates); latency_n256: the single small "
-                           "FP64 solve; serving: the compact continuous-batching leg",
+                           "FP64 solve; large_n30000: the large single solve; serving: the "
+                           "compact continuous-batching leg",
     }
     if not args.no_legs:
         log("latency leg")
         out["latency_n256"] = latency_leg(fdm, torch)
+        out["large_n30000"] = large_leg(fdm, torch)
         log("compact serving leg")
         leg = argparse.Namespace(**vars(args))
         leg.requests, leg.n_min, leg.n_max = args.leg_requests, 500, 16000

@@ -157,6 +157,51 @@ def cpu_baseline(wl, iters_per_solve, budget_s=15.0):
     return dict(value=value, unit="solves/s", cores=int(cores), kind="oracle", sample=sample)
 
 
+def diagonalization_leg(torch, wl, budget_s=3.0):
+    """The explicit diagonalization that the expansion replaces (Sec. I and
+    Sec. III.A; the paper compares against ELPA), on the same Hp: LAPACK
+    dsyevd through numpy on the host cores, and torch.linalg.eigh on the GPU,
+    each followed by D = Q_occ Q_occ^T.  Context only: neither is part of
+    the library."""
+    import numpy as np
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    k = int(wl.n_occ)
+    e_ref = float(np.sort(wl.lam)[:k].sum())
+    out = {"workload": f"n{wl.n}-nocc{k}"}
+    times = []
+    while not times or (sum(times) < budget_s and len(times) < 3):
+        t0 = time.perf_counter()
+        w, v = np.linalg.eigh(wl.hp)
+        d = v[:, :k] @ v[:, :k].T
+        times.append(time.perf_counter() - t0)
+    out["cpu_lapack_eigh"] = dict(ms_per_solve=round(1e3 * float(np.median(times)), 2),
+                                  solves_per_s=round(1.0 / float(np.median(times)), 4),
+                                  cores=int(cores), runs=len(times),
+                                  abs_dE_Ha=float(f"{abs(w[:k].sum() - e_ref):.3e}"))
+    del d, v
+    H = torch.from_numpy(wl.hp).cuda()
+    w2, v2 = torch.linalg.eigh(H)   # warm-up (library set-up)
+    torch.cuda.synchronize()
+    reps, t0 = 0, time.perf_counter()
+    while reps < 3 or (time.perf_counter() - t0 < budget_s and reps < 50):
+        w2, v2 = torch.linalg.eigh(H)
+        q = v2[:, :k]
+        D = q @ q.T
+        torch.cuda.synchronize()
+        reps += 1
+    dt = (time.perf_counter() - t0) / reps
+    out["gpu_torch_eigh"] = dict(ms_per_solve=round(1e3 * dt, 2), solves_per_s=round(1.0 / dt, 4),
+                                 runs=reps,
+                                 abs_dE_Ha=float(f"{abs(float(w2[:k].sum()) - e_ref):.3e}"))
+    del H, D, q, v2
+    torch.cuda.empty_cache()
+    return out
+
+
 def latency_leg(fdm, torch, solves=200):
     """The single small solve: N = 256, n_occ = 64, gap 0.2 Ha, plain FP64
     SP2 (Gershgorin and certified-Lanczos bounds), microseconds per solve
@@ -491,11 +536,16 @@ def main():
         "extra_keys_note": "forms: every measured form with its quality_last_solve (Sec. III.C "
                            "eps1, eps2 and the absolute gates); latency_n256: the single small "
                            "FP64 solve; large_n30000: the large single solve; serving: the "
-                           "compact continuous-batching leg",
+                           "compact continuous-batching leg; diagonalization: explicit "
+                           "eigensolver baselines on the same matrices (LAPACK on the host, "
+                           "torch.linalg.eigh on the GPU), context only",
     }
     if not args.no_legs:
         log("latency leg")
         out["latency_n256"] = latency_leg(fdm, torch)
+        log("diagonalization baselines")
+        out["diagonalization"] = [diagonalization_leg(torch, workloads.standard_workload("gapped")),
+                                  diagonalization_leg(torch, wl)]
         out["large_n30000"] = large_leg(fdm, torch)
         log("compact serving leg")
         leg = argparse.Namespace(**vars(args))

@@ -341,7 +341,9 @@ int fdm_poll(fdm_server *s, uint64_t ticket);
 /* Blocks until the request finishes, copies D to D_out (host memory if
  * out_on_host, else device; leading dimension ldd) and releases it.
  * Returns the request's solve status.  times (host double[4], nullable):
- * submit, start, finish and result times in seconds on the server clock. */
+ * submit, start, finish and result times in seconds on the server clock.
+ * A ticket is collected once: a second call for it, concurrent or later,
+ * returns FDM_EINVAL. */
 int fdm_result(fdm_server *s, uint64_t ticket, double *D_out, int32_t out_on_host,
                int64_t ldd, double *E_band, fdm_stats *stats, double *times);
 

@@ -361,10 +361,16 @@ int fdm_result(fdm_server *s, uint64_t ticket, double *D_out, int32_t out_on_hos
     set_error("");
     if (!s) return FDM_EINVAL;
     std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->reqs.find(ticket);
-    if (it == s->reqs.end() || it->second->collecting) return FDM_EINVAL;
-    Request *r = it->second.get();
-    while (r->status == 1) s->cv.wait(lk);
+    // Look the ticket up again after every wait: another fdm_result call on
+    // the same ticket may have collected (and erased) it meanwhile.
+    Request *r = nullptr;
+    while (true) {
+        auto it = s->reqs.find(ticket);
+        if (it == s->reqs.end() || it->second->collecting) return FDM_EINVAL;
+        r = it->second.get();
+        if (r->status != 1) break;
+        s->cv.wait(lk);
+    }
     if (D_out && ldd < r->n) return FDM_EINVAL;
     // copy D out without the lock: the other requests keep running and
     // being admitted meanwhile

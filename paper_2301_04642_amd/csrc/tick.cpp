@@ -20,6 +20,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <tuple>
 #include <vector>
@@ -38,6 +39,7 @@ struct TickGroup {
     std::vector<TickMember *> members;
     bool stop = false;
     int error = 0;
+    std::string error_msg;          // the ticker's message for the failed members
     std::thread ticker;
     void run();
 };
@@ -171,7 +173,10 @@ void TickGroup::run() {
             if (tk.size() > 1) t.m->shared += 1;
             if (rc) t.m->error = rc;
         }
-        if (rc) error = rc;
+        if (rc) {
+            error = rc;
+            error_msg = last_error();  // set on this thread; members report it on theirs
+        }
         cv.notify_all();
     }
 }
@@ -179,10 +184,16 @@ void TickGroup::run() {
 TickGroup *tick_group_create(int device) {
     std::unique_ptr<TickGroup> g(new TickGroup());
     g->device = device;
-    if (hipStreamCreateWithFlags(&g->gs, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    auto undo = [&g] {
+        for (hipEvent_t e : g->tick_ev)
+            if (e) (void)hipEventDestroy(e);
+        if (g->gs) (void)hipStreamDestroy(g->gs);
+        return nullptr;
+    };
+    if (hipStreamCreateWithFlags(&g->gs, hipStreamNonBlocking) != hipSuccess) return undo();
     for (int i = 0; i < 2; ++i)
         if (hipEventCreateWithFlags(&g->tick_ev[i], hipEventDisableTiming) != hipSuccess)
-            return nullptr;
+            return undo();
     TickGroup *raw = g.get();
     g->ticker = std::thread([raw] { raw->run(); });
     return g.release();
@@ -225,7 +236,10 @@ int tick_wait(TickGroup *g, TickMember *m, int seq) {
     {
         std::unique_lock<std::mutex> lk(g->mu);
         g->cv.wait(lk, [&] { return m->launched >= seq || m->error != 0 || g->stop; });
-        if (m->error) return m->error;
+        if (m->error) {
+            set_error(g->error_msg);
+            return m->error;
+        }
         if (m->launched < seq) {
             set_error("serving tick group stopped");
             return FDM_EHIP;
@@ -244,7 +258,10 @@ int tick_leave(TickGroup *g, TickMember *m) {
         // a step the ticker has taken is launched before the member may go
         g->cv.wait(lk, [&] { return m->taken == 0; });
         last = m->launched;
-        if (m->error) return m->error;
+        if (m->error) {
+            set_error(g->error_msg);
+            return m->error;
+        }
     }
     if (last < 0) return FDM_OK;
     hipError_t e = hipEventSynchronize(m->ev[last % kEvRing]);

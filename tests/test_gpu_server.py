@@ -2,6 +2,7 @@
 requests.  Each result equals the same request solved alone (bitwise: every
 solve is deterministic and independent of what else runs); the budget is
 enforced at submission and at admission."""
+import threading
 import time
 
 import numpy as np
@@ -162,6 +163,27 @@ def test_budget_enforced(fdm):
         spans.sort()
         for (s0, f0), (s1, f1) in zip(spans, spans[1:]):
             assert s1 >= f0
+    finally:
+        srv.close()
+
+
+def test_result_collected_once(fdm):
+    """Two threads collect the same ticket at once: one gets the result, the
+    other FDM_EINVAL, and so does a later call."""
+    wl = workloads.standard_workload("gapped", n=400)
+    srv = fdm.Server(budget_bytes=1 << 30, max_active=2, precision="fp32")
+    try:
+        say("collect once")
+        t = srv.submit(wl.hp, wl.n_occ, 0.0, 1e-8)
+        out = []
+        ths = [threading.Thread(target=lambda: out.append(srv.result(t, wl.n)[0]))
+               for _ in range(2)]
+        for th in ths:
+            th.start()
+        for th in ths:
+            th.join(timeout=120)
+        assert sorted(out) == [fdm.FDM_EINVAL, 0]
+        assert srv.result(t, wl.n)[0] == fdm.FDM_EINVAL
     finally:
         srv.close()
 

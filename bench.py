@@ -53,8 +53,11 @@ def measured_traffic(prec):
     return rec.get("traffic_bytes_per_launch", {}).get(prec)
 
 
+_T0 = time.perf_counter()
+
+
 def log(*a):
-    print("[bench]", *a, file=sys.stderr, flush=True)
+    print(f"[bench {time.perf_counter() - _T0:7.1f}s]", *a, file=sys.stderr, flush=True)
 
 
 def parse_form(form):
@@ -279,13 +282,18 @@ def large_leg(fdm, torch):
 
 
 def serving(args, precisions=None, log_every=8):
-    """precisions: served forms, each a precision name, optionally suffixed
-    "+independent" (each request on its own stream instead of grouped
-    ticks)."""
     """Continuous-batching server under Poisson arrivals: closed-loop
     capacity, then an open loop at args.load x capacity (p50/p99 latency,
-    solves/s), for each served precision, against one-at-a-time FP64 solves
-    of the same requests.  Returns a dict."""
+    solves/s), for each served form, against one-at-a-time FP64 solves of (a
+    sample of) the same requests.  precisions: served forms, each a precision
+    name, optionally suffixed "+independent" (each request on its own stream
+    instead of grouped ticks).  Request matrices are built at submission
+    (signed permutations of seeded templates) and results are collected by a
+    second thread as they finish, so host memory and the server's budget
+    hold only the requests in flight.  Returns a dict."""
+    import queue
+    import threading
+
     import numpy as np
     import torch
 
@@ -296,9 +304,8 @@ def serving(args, precisions=None, log_every=8):
     torch.cuda.set_device(0)
     precisions = precisions or [args.serve_precision]
     rng = np.random.default_rng(4_999_999)
-    ntemp = 6
     ns = sorted(set(int(x) for x in np.exp(rng.uniform(np.log(args.n_min), np.log(args.n_max),
-                                                        ntemp))))
+                                                        args.templates))))
     templates = {}
     log("building", len(ns) * 2, "templates")
     for i, n in enumerate(ns):
@@ -308,47 +315,104 @@ def serving(args, precisions=None, log_every=8):
             log(f"  template n={n} {kind}")
             wl = workloads.serving_workload(req)
             f, _ = den.occupations(wl.lam, wl.n_occ, wl.kT)
-            templates[(n, kind)] = (wl, float(np.dot(f, wl.lam)))
+            templates[(n, kind)] = (wl.hp, wl.n_occ, wl.kT, float(np.dot(f, wl.lam)))
+            del wl
+    # request r: template (n, kind) and the seed of its signed permutation
     reqs = []
     for r in range(args.requests):
         n = ns[rng.integers(len(ns))]
-        kind = "gapped" if r % 2 == 0 else "metallic"
-        wl, e_ref = templates[(n, kind)]
-        perm = rng.permutation(n)
-        sign = rng.choice([-1.0, 1.0], n)
-        hp = (wl.hp[np.ix_(perm, perm)] * sign[:, None]) * sign[None, :]
-        reqs.append(dict(n=n, n_occ=wl.n_occ, kT=wl.kT, hp=np.ascontiguousarray(hp), e_ref=e_ref))
+        reqs.append(dict(n=n, kind="gapped" if r % 2 == 0 else "metallic",
+                         seed=int(rng.integers(1 << 62))))
+
+    def matrix(q):
+        hp = templates[(q["n"], q["kind"])][0]
+        g = np.random.default_rng(q["seed"])
+        perm = g.permutation(q["n"])
+        sign = g.choice([-1.0, 1.0], q["n"])
+        return np.ascontiguousarray((hp[np.ix_(perm, perm)] * sign[:, None]) * sign[None, :])
+
     budget = int(args.budget_gb * (1 << 30))
     arrival_rng = np.random.default_rng(4_999_998)
+    window = 2 * args.max_active    # closed loop: requests outstanding at once
 
     def run(arrivals, form):
+        """arrivals None: closed loop with `window` requests outstanding."""
         prec, *mods = form.split("+")
         grouped = not (args.serve_independent or "independent" in mods)
         srv = fdm.Server(budget_bytes=budget, max_active=args.max_active, precision=prec,
                          grouped=grouped)
+        tickets = [None] * len(reqs)
+        submitted = threading.Semaphore(0)
+        free = threading.Semaphore(window if arrivals is None else len(reqs) + 1)
+        res = dict(lat=[], worst=0.0, error=None)
+
+        def collect():
+            try:
+                for k, q in enumerate(reqs):
+                    submitted.acquire()
+                    if k % log_every == 0:
+                        log(f"  collecting result {k} / {len(reqs)}")
+                    _, n_occ, kT, e_ref = templates[(q["n"], q["kind"])]
+                    rc, d, e, st, times = srv.result(tickets[k], q["n"])
+                    free.release()
+                    if rc != 0:
+                        raise RuntimeError(f"request {k}: status {rc}")
+                    res["worst"] = max(res["worst"], abs(e - e_ref))
+                    res["lat"].append(times[2] - times[0])
+            except Exception as exc:      # reported by the submitting thread
+                res["error"] = exc
+                for _ in range(len(reqs)):
+                    free.release()
+
+        # matrices are built a few requests ahead, so that building a large
+        # one does not delay an arrival
+        ahead = queue.Queue(maxsize=6)
+        stop = threading.Event()
+
+        def produce():
+            for q in reqs:
+                if stop.is_set():
+                    return
+                ahead.put(matrix(q))
+
+        prod = threading.Thread(target=produce, daemon=True)
+        prod.start()
+        th = threading.Thread(target=collect, daemon=True)
+        th.start()
         t0 = time.perf_counter()
-        tickets = []
-        for q, at in zip(reqs, arrivals):
-            while time.perf_counter() - t0 < at:
-                time.sleep(0.0005)
-            tickets.append(srv.submit(q["hp"], q["n_occ"], q["kT"], 1e-8))
-        lat, worst = [], 0.0
-        for k, (t, q) in enumerate(zip(tickets, reqs)):
-            if k % log_every == 0:
-                log(f"  collecting result {k} / {len(reqs)}")
-            rc, d, e, st, times = srv.result(t, q["n"])
-            assert rc == 0, rc
-            worst = max(worst, abs(e - q["e_ref"]))
-            lat.append(times[2] - times[0])
+        for k, q in enumerate(reqs):
+            hp = ahead.get()
+            free.acquire()
+            if res["error"] is not None:
+                break
+            if arrivals is not None:
+                while time.perf_counter() - t0 < arrivals[k]:
+                    time.sleep(0.0005)
+            _, n_occ, kT, _ = templates[(q["n"], q["kind"])]
+            tickets[k] = srv.submit(hp, n_occ, kT, 1e-8)
+            del hp
+            submitted.release()
+        stop.set()
+        while prod.is_alive():          # unblock a producer waiting on a full queue
+            try:
+                ahead.get_nowait()
+            except queue.Empty:
+                time.sleep(0.01)
+        th.join()
+        span = time.perf_counter() - t0
         held, _, _ = srv.memory()
         srv.close()
-        return np.array(lat), worst, time.perf_counter() - t0, held
+        if res["error"] is not None:
+            raise res["error"]
+        return np.array(res["lat"]), res["worst"], span, held
 
     per_prec = {}
     for prec in precisions:
-        log(f"serving {prec}: closed loop (all requests at t = 0)")
-        lat0, worst0, span0, held0 = run([0.0] * len(reqs), prec)
+        log(f"serving {prec}: closed loop ({window} requests outstanding)")
+        lat0, worst0, span0, held0 = run(None, prec)
         capacity = len(reqs) / span0
+        log(f"serving {prec}: closed loop {capacity:.3f} solves/s, p50 "
+            f"{np.percentile(lat0, 50):.3f} s, p99 {np.percentile(lat0, 99):.3f} s")
         rate = args.load * capacity
         gaps = arrival_rng.exponential(1.0 / rate, len(reqs))
         arrivals = list(np.cumsum(gaps) - gaps[0])
@@ -366,23 +430,29 @@ def serving(args, precisions=None, log_every=8):
             "worst_abs_dE_Ha": max(worst, worst0),
             "held_device_bytes_at_end": max(held, held0),
         }
-    log("one at a time, fp64")
+        log(f"serving {prec}:", json.dumps(per_prec[prec]))
+    sample = reqs[:min(len(reqs), args.seq_sample)]
+    log(f"one at a time, fp64 ({len(sample)} requests)")
     t0 = time.perf_counter()
-    for k, q in enumerate(reqs):
+    for k, q in enumerate(sample):
         if k % log_every == 0:
-            log(f"  request {k} / {len(reqs)}")
-        H = torch.from_numpy(q["hp"]).cuda()
-        fdm.solve(H, q["n_occ"], q["kT"], 1e-8, "fp64")
+            log(f"  request {k} / {len(sample)}")
+        _, n_occ, kT, _ = templates[(q["n"], q["kind"])]
+        H = torch.from_numpy(matrix(q)).cuda()
+        fdm.solve(H, n_occ, kT, 1e-8, "fp64")
+        del H
     torch.cuda.synchronize()
-    seq = len(reqs) / (time.perf_counter() - t0)
+    seq = len(sample) / (time.perf_counter() - t0)
     return {
         "metric": "serving: solves/s and latency under Poisson arrivals", "unit": "solves/s",
         "requests": len(reqs), "n_range": [args.n_min, args.n_max], "distinct_n": ns,
         "max_active": args.max_active, "budget_gb": args.budget_gb, "load": args.load,
+        "closed_loop_window": window,
         "ticks": "independent streams" if args.serve_independent else
                  "grouped (one product launch per precision and one decision launch per tick)",
         "forms": per_prec,
         "sequential_fp64_solves_per_s": round(seq, 3),
+        "sequential_fp64_requests": len(sample),
         "data": "synthetic (signed permutations of seeded templates; half gapped 0.1 Ha at "
                 "kT = 0, half metallic at kT = 0.0016 Ha)",
     }
@@ -415,6 +485,10 @@ def main():
     ap.add_argument("--serve-independent", action="store_true",
                     help="serve with each request on its own stream (no grouped ticks)")
     ap.add_argument("--load", type=float, default=0.8)
+    ap.add_argument("--templates", type=int, default=6,
+                    help="distinct sizes drawn for the serving requests")
+    ap.add_argument("--seq-sample", type=int, default=64,
+                    help="requests solved one at a time in FP64 for the serving baseline")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the N = 256 latency leg and the compact serving leg")
     ap.add_argument("--latency-only", action="store_true",

@@ -104,7 +104,9 @@ typedef struct fdm_options {
                                n_occ or stall; the solve then repeats as plain SP2.  NaN
                                (default) = plain SP2                                           */
     double mu_guess;        /* finite T: start of the mu search (e.g. the previous SCF step's mu);
-                               NaN (default) = the guess from the moments of Hp                */
+                               the mixed forms then skip their low-precision search and start
+                               with the FP64 evaluation.  NaN (default) = the guess from the
+                               moments of Hp                                                   */
     void *workspace;        /* optional caller-owned device memory of workspace_bytes, 256-byte
                                aligned (FDM_EINVAL otherwise)                                   */
     size_t workspace_bytes; /* at least fdm_workspace_bytes(N, kT, precision)                  */

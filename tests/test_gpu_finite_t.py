@@ -112,15 +112,19 @@ def test_solve_mixed_final_fp64(fdm, prec):
     assert st.products[fdm.PRECISIONS[prec]] > 0 and st.products[0] > 0
 
 
-def test_mu_guess_from_a_previous_solve(fdm):
+@pytest.mark.parametrize("prec", ["fp64", "fp16x3"])
+def test_mu_guess_from_a_previous_solve(fdm, prec):
     """Started from the mu of an earlier solve of the same matrix (an SCF
-    step), the search ends after one evaluation with the same result."""
+    step), the search ends after one evaluation with the same result; the
+    mixed form then goes straight to its FP64 evaluation."""
     wl = workloads.standard_workload("uniform", n=600)
     H = dev(wl.hp)
     D0, e0, st0 = fdm.solve(H, wl.n_occ, wl.kT, 1e-9, "fp64")
-    D1, e1, st1 = fdm.solve(H, wl.n_occ, wl.kT, 1e-9, "fp64", mu_guess=st0.mu)
-    print(f"[report] mu guess: evals {st0.mu_evals} -> {st1.mu_evals}, |dE|={abs(e1 - e0):.1e}",
-          flush=True)
+    D1, e1, st1 = fdm.solve(H, wl.n_occ, wl.kT, 1e-9, prec, mu_guess=st0.mu)
+    print(f"[report] mu guess ({prec}): evals {st0.mu_evals} -> {st1.mu_evals}, "
+          f"|dE|={abs(e1 - e0):.1e}", flush=True)
     assert st1.status == 0 and st1.mu_evals <= 2 < st0.mu_evals
+    if prec != "fp64":
+        assert st1.products[fdm.PRECISIONS[prec]] == 0 and st1.products[0] > 0
     assert abs(e1 - e0) <= 1e-9 and abs(st1.mu - st0.mu) <= 1e-9
     assert float((D1 - D0).abs().max()) <= 1e-9

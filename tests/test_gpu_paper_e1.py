@@ -76,9 +76,10 @@ def test_e1_finite_t(fdm, e1, prec):
                            mu_guess=st.mu)
     print(f"[report]   from the previous mu: evals {st2.mu_evals} {st2.ms_total:.0f} ms "
           f"|dE|={abs(e2 - e_ref):.2e}", flush=True)
-    # (the mixed form still searches in low precision, whose trace noise
-    # leaves its mu about 1e-3 kT from the FP64 one: one or two more)
-    assert st2.status == 0 and st2.mu_evals <= (2 if prec == "fp64" else 4)
+    # with a guess the mixed form starts with the FP64 evaluation (no
+    # low-precision search)
+    assert st2.status == 0 and st2.mu_evals <= 2
+    assert st2.products[fdm.PRECISIONS[prec]] == 0 or prec == "fp64"
     assert abs(e2 - e_ref) <= (1e-9 if prec == "fp64" else 1e-6)
 
 

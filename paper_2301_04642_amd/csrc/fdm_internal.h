@@ -37,6 +37,17 @@ inline int64_t tile_rows(int64_t n, int bt) {
     return bt == 32 ? (n + 63) / 64 * 2 : (n + bt - 1) / bt;
 }
 
+// 128-wide split products whose K extent round_up(n, 64) ends 64 columns
+// into the last tile column cover that column with 256 x 64 edge blocks
+// (two tile rows each) instead of half-padding 128-wide tiles: list entries
+// upper_tiles(T - 1) followed by (1 << 31) | (q << 16) | (T - 1) for
+// q < ceil(T / 2), T = tile_rows(n, 128).
+inline bool edge_blocks(int64_t n) { return (n + 63) / 64 % 2 == 1; }
+inline int64_t edge_ntiles(int64_t n) {
+    const int64_t t = tile_rows(n, 128);
+    return (t - 1) * t / 2 + (t + 1) / 2;
+}
+
 // Tile edge (32, 64 or 128) of a product of size n in precision prec; forced
 // = 32 (n <= kTile32MaxN), 64 or 128 overrides the measured choice.
 int choose_tile(int64_t n, int prec, int forced);

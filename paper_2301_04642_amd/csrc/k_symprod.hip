@@ -209,8 +209,24 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return (xcd < rem) ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
 }
 
-// One output tile (entry t of a.tiles) of one product.
-template <int P, int BT, bool DMA>
+// LDS of the 128-wide split kernels, shared by their two block shapes (one
+// allocation per kernel: two blocks of 80 KiB per CU).
+constexpr int kEdgePoolBytes = 2 * (256 + 64) * 128;
+__device__ __forceinline__ unsigned char *lds_pool() {
+    __shared__ __attribute__((aligned(16))) unsigned char pool[kEdgePoolBytes];
+    return pool;
+}
+
+// One output tile (entry t of a.tiles) of one product.  KIND 0: a BT x BT
+// tile with LDS of its own; KIND 1: the same from the shared pool; KIND 2
+// (128-wide split forms, direct-to-LDS staging): an edge block of 256 x 64
+// outputs, rows 256 q .. and columns 128 tj .. of an entry (1 << 31) |
+// (q << 16) | tj, covering the last tile column where the padded extent
+// ends 64 columns into it.  Its four waves are stacked (64 x 64 each, the
+// same per-wave work and accumulation order as a 128-wide tile); a wave
+// whose rows start below the block's columns (lower triangle) stores
+// nothing.
+template <int P, int BT, bool DMA, int KIND = 0>
 __device__ __forceinline__ void symprod_tile(const ProdArgs &a, const int t) {
     using T = PT<P>;
     using S = typename T::S;
@@ -237,12 +253,24 @@ __device__ __forceinline__ void symprod_tile(const ProdArgs &a, const int t) {
     constexpr int FM = WT / 16;
 
     static_assert(!DMA || SWZ, "direct-to-LDS staging needs the swizzled rows");
-    __shared__ __attribute__((aligned(16))) unsigned char lds[2 * 2 * PANEL];
+    static_assert(KIND == 0 || (BT == 128 && DMA), "edge blocks: 128-wide, direct to LDS");
+    constexpr bool TALL = (KIND == 2);
+    constexpr int AROWS = TALL ? 256 : BT;         // operand rows staged per stage
+    constexpr int BROWS = TALL ? 64 : BT;
+    constexpr int STAGE = (AROWS + BROWS) * RSB;   // bytes of one LDS stage
+    unsigned char *lds;
+    if constexpr (KIND == 0) {
+        __shared__ __attribute__((aligned(16))) unsigned char own[2 * 2 * PANEL];
+        lds = own;
+    } else {
+        static_assert(2 * STAGE <= kEdgePoolBytes, "pool");
+        lds = lds_pool();
+    }
 
     const int tid = threadIdx.x;
     const uint32_t tt = a.tiles[t];
-    const int ti = (int)(tt >> 16), tj = (int)(tt & 0xffffu);
-    const int64_t row0 = (int64_t)ti * BT, col0 = (int64_t)tj * BT;
+    const int ti = (int)(TALL ? ((tt >> 16) & 0x7fffu) : (tt >> 16)), tj = (int)(tt & 0xffffu);
+    const int64_t row0 = (int64_t)ti * (TALL ? 256 : BT), col0 = (int64_t)tj * BT;
     const int64_t ld = a.ld;
     const S *__restrict__ A = (const S *)a.A;
     const S *__restrict__ B = (const S *)a.B;
@@ -297,7 +325,7 @@ __device__ __forceinline__ void symprod_tile(const ProdArgs &a, const int t) {
     };
 
     const int w = tid >> 6, lane = tid & 63;
-    const int wr = w >> 1, wc = w & 1, lr = lane & 15, lg = lane >> 4;
+    const int wr = TALL ? w : w >> 1, wc = TALL ? 0 : w & 1, lr = lane & 15, lg = lane >> 4;
     // Direct-to-LDS staging (global_load_lds_dwordx4): lane l of a wave
     // instruction writes LDS bytes [16 l, 16 l + 16) of a 1 KiB block, i.e.
     // slot l & 7 of row l >> 3 of an 8-row group, so it fetches chunk
@@ -305,11 +333,19 @@ __device__ __forceinline__ void symprod_tile(const ProdArgs &a, const int t) {
     // the same swizzled rows as the register path.
     auto dload = [&](int kt, int st) {
         constexpr int QB = BT / 8;                 // 8-row groups per operand panel
+        constexpr int QA = AROWS / 8, NG = (AROWS + BROWS) / 8;   // (edge blocks)
+        static_assert(NG % 4 == 0, "groups per wave");
 #pragma unroll
-        for (int u = 0; u < QB / 2; ++u) {
+        for (int u = 0; u < NG / 4; ++u) {
             const int j = w + 4 * u;               // wave-uniform
-            const int op = j / QB, q = j % QB;
-            const int64_t row = (op ? col0 : row0) + 8 * q + (lane >> 3);
+            const int op = TALL ? (j >= QA ? 1 : 0) : j / QB;
+            const int q = TALL ? (op ? j - QA : j) : j % QB;
+            int64_t base = (op ? col0 : row0) + 8 * q;
+            // the last edge block of an odd tile count reaches 128 rows past
+            // the padded matrix (ld rows): its waves there store nothing,
+            // and they stage in-range rows instead
+            if (TALL && !op && base >= ld) base -= 128;
+            const int64_t row = base + (lane >> 3);
             const int chunk = (lane & 7) ^ (lane >> 3);
             const void *src;
             if constexpr (SPLIT)
@@ -318,7 +354,9 @@ __device__ __forceinline__ void symprod_tile(const ProdArgs &a, const int t) {
                 src = (op ? B : A) + row * ld + (int64_t)kt * KST + chunk * EPC;
             __builtin_amdgcn_global_load_lds(
                 src,
-                (__attribute__((address_space(3))) void *)(lds + (st * 2 + op) * PANEL + q * 1024),
+                (__attribute__((address_space(3))) void *)(
+                    TALL ? lds + st * STAGE + op * AROWS * RSB + q * 1024
+                         : lds + (st * 2 + op) * PANEL + q * 1024),
                 16, 0, 0);
         }
     };
@@ -356,8 +394,8 @@ __device__ __forceinline__ void symprod_tile(const ProdArgs &a, const int t) {
         }
 
     auto compute = [&](int st, int kt) {
-        const unsigned char *pa = lds + (st * 2 + 0) * PANEL;
-        const unsigned char *pb = lds + (st * 2 + 1) * PANEL;
+        const unsigned char *pa = TALL ? lds + st * STAGE : lds + (st * 2 + 0) * PANEL;
+        const unsigned char *pb = TALL ? lds + st * STAGE + AROWS * RSB : lds + (st * 2 + 1) * PANEL;
 #pragma unroll
         for (int g = 0; g < GROUPS; ++g) {
             u4_t fa[FM], fb[FM], fal[FM], fbl[FM];
@@ -480,66 +518,70 @@ __device__ __forceinline__ void symprod_tile(const ProdArgs &a, const int t) {
     const double scale = (HALF && T::F16) ? kF16Unscale : 1.0;
     const S *__restrict__ E = (const S *)a.E;
     S *__restrict__ C = (S *)a.C;
-    const bool diag = (ti == tj);
+    // a tall edge block's wave covers rows row0 + 64 wr .. of its column block
+    const bool diag = TALL ? (row0 + 64 * wr == col0) : (ti == tj);
+    const bool active = !TALL || row0 + 64 * wr <= col0;
     double s_tr = 0.0, s_f2 = 0.0, s_d2 = 0.0;
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < FM; ++i) {
+        for (int i = 0; i < FM; ++i) {
 #pragma unroll
-        for (int j = 0; j < FM; ++j) {
-            const int64_t rb = row0 + wr * WT + i * 16;
-            const int64_t col = col0 + wc * WT + j * 16 + lr;
-            S ov[4];
+            for (int j = 0; j < FM; ++j) {
+                const int64_t rb = row0 + wr * WT + i * 16;
+                const int64_t col = col0 + wc * WT + j * 16 + lr;
+                S ov[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t row = rb + (ROWS_CONSECUTIVE ? 4 * lg + q : lg + 4 * q);
-                const double v = ((double)acc[i][j][q] - (double)cmp[i][j][q]) * scale;
-                const double e = (E != nullptr) ? (double)E[row * ld + col] : 0.0;
-                double o = alpha * v + beta * e;
-                if (row == col && row < a.n) o += gamma;
-                const S os = (S)o;
-                ov[q] = os;
-                // Off-diagonal tiles: every element, stored twice (mirror).
-                // Diagonal tiles: only row <= col is kept and mirrored, so C
-                // is exactly symmetric even where (i,j) and (j,i) were
-                // accumulated in different orders.
-                const double w = diag ? (row < col ? 2.0 : (row == col ? 1.0 : 0.0)) : 2.0;
-                if (w != 0.0) {
-                    C[row * ld + col] = os;
-                    if (diag && row < col) C[col * ld + row] = os;
-                    if constexpr (SPLIT) {
-                        uint16_t h, l;
-                        split1<P>((float)os, h, l);
-                        const int64_t k = hl_index(row, col, ld);
-                        a.Chl[k] = h;
-                        a.Chl[k + 32] = l;
-                        if (diag && row < col) {
-                            const int64_t km = hl_index(col, row, ld);
-                            a.Chl[km] = h;
-                            a.Chl[km + 32] = l;
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t row = rb + (ROWS_CONSECUTIVE ? 4 * lg + q : lg + 4 * q);
+                    const double v = ((double)acc[i][j][q] - (double)cmp[i][j][q]) * scale;
+                    const double e = (E != nullptr) ? (double)E[row * ld + col] : 0.0;
+                    double o = alpha * v + beta * e;
+                    if (row == col && row < a.n) o += gamma;
+                    const S os = (S)o;
+                    ov[q] = os;
+                    // Off-diagonal tiles: every element, stored twice (mirror).
+                    // Diagonal tiles: only row <= col is kept and mirrored, so C
+                    // is exactly symmetric even where (i,j) and (j,i) were
+                    // accumulated in different orders.
+                    const double w = diag ? (row < col ? 2.0 : (row == col ? 1.0 : 0.0)) : 2.0;
+                    if (w != 0.0) {
+                        C[row * ld + col] = os;
+                        if (diag && row < col) C[col * ld + row] = os;
+                        if constexpr (SPLIT) {
+                            uint16_t h, l;
+                            split1<P>((float)os, h, l);
+                            const int64_t k = hl_index(row, col, ld);
+                            a.Chl[k] = h;
+                            a.Chl[k + 32] = l;
+                            if (diag && row < col) {
+                                const int64_t km = hl_index(col, row, ld);
+                                a.Chl[km] = h;
+                                a.Chl[km + 32] = l;
+                            }
                         }
+                        const double od = (double)os;
+                        if (row == col) s_tr += od;
+                        s_f2 += w * od * od;
+                        s_d2 += w * (v - e) * (v - e);
                     }
-                    const double od = (double)os;
-                    if (row == col) s_tr += od;
-                    s_f2 += w * od * od;
-                    s_d2 += w * (v - e) * (v - e);
                 }
-            }
-            if (!diag) {
-                if constexpr (ROWS_CONSECUTIVE) {
-                    S *dst = C + col * ld + rb + 4 * lg;
-                    *(f4_t *)dst = f4_t{(float)ov[0], (float)ov[1], (float)ov[2], (float)ov[3]};
-                    if constexpr (SPLIT) {
-                        u2_t hi4, lo4;
-                        to_halves<P>(bitcast<u4_t>(f4_t{(float)ov[0], (float)ov[1], (float)ov[2],
-                                                        (float)ov[3]}),
-                                     hi4, lo4);
-                        const int64_t m = hl_index(col, rb + 4 * lg, ld);
-                        *(u2_t *)(a.Chl + m) = hi4;
-                        *(u2_t *)(a.Chl + m + 32) = lo4;
-                    }
-                } else {
+                if (!diag) {
+                    if constexpr (ROWS_CONSECUTIVE) {
+                        S *dst = C + col * ld + rb + 4 * lg;
+                        *(f4_t *)dst = f4_t{(float)ov[0], (float)ov[1], (float)ov[2], (float)ov[3]};
+                        if constexpr (SPLIT) {
+                            u2_t hi4, lo4;
+                            to_halves<P>(bitcast<u4_t>(f4_t{(float)ov[0], (float)ov[1], (float)ov[2],
+                                                            (float)ov[3]}),
+                                         hi4, lo4);
+                            const int64_t m = hl_index(col, rb + 4 * lg, ld);
+                            *(u2_t *)(a.Chl + m) = hi4;
+                            *(u2_t *)(a.Chl + m + 32) = lo4;
+                        }
+                    } else {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) C[col * ld + rb + lg + 4 * q] = ov[q];
+                        for (int q = 0; q < 4; ++q) C[col * ld + rb + lg + 4 * q] = ov[q];
+                    }
                 }
             }
         }
@@ -576,10 +618,24 @@ __device__ __forceinline__ void symprod_tile(const ProdArgs &a, const int t) {
         BT == 32 ? 8 : BT == 64 ? 4 : ((P == P_F32 || P == P_F64 || PT<P>::SPLIT) ? 2 : 1), \
         BT == 32 ? 8 : BT == 64 ? 4 : ((P == P_F32 || P == P_F64 || PT<P>::SPLIT) ? 2 : 1))))
 
+// One list entry: a tile, or for the 128-wide split forms staged straight
+// into LDS an edge block (bit 31 of the entry) as well.
+template <int P, int BT, bool DMA>
+__device__ __forceinline__ void symprod_entry(const ProdArgs &a, const int t) {
+    if constexpr (PT<P>::SPLIT && BT == 128 && DMA) {
+        if (a.tiles[t] >> 31)
+            symprod_tile<P, 128, true, 2>(a, t);
+        else
+            symprod_tile<P, 128, true, 1>(a, t);
+    } else {
+        symprod_tile<P, BT, DMA>(a, t);
+    }
+}
+
 template <int P, int BT, bool DMA>
 __global__ FDM_SYMPROD_ATTRS(P, BT) void k_symprod(ProdArgs a) {
     if (a.done != nullptr && *a.done) return;
-    symprod_tile<P, BT, DMA>(a, xcd_remap(blockIdx.x, gridDim.x));
+    symprod_entry<P, BT, DMA>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // Several products of one precision, tile edge and staging path in one
@@ -594,7 +650,7 @@ __global__ FDM_SYMPROD_ATTRS(P, BT) void k_symprod_grouped(ProdGroup g) {
     while (j + 1 < g.njobs && u >= g.first[j + 1]) ++j;
     const ProdArgs &a = g.job[j];
     if (a.done != nullptr && *a.done) return;
-    symprod_tile<P, BT, DMA>(a, u - g.first[j]);
+    symprod_entry<P, BT, DMA>(a, u - g.first[j]);
 }
 
 // Staging path (measured on MI355X, SP2 solves of the paper's matrix):

@@ -103,6 +103,7 @@ int fdm_sym_product_noalloc(int32_t precision, const double *A, const double *B,
     Resources r;
     r.device = dev;
     r.view(L, mem);
+    r.tiles128e = nullptr;  // no edge-block list here: 128-wide tiles only
     r.st_pinned = &r.st_fallback;
     const size_t words = L.bytes / 16;
     const int blocks = (int)std::min<size_t>((words + 255) / 256, 2048);

@@ -93,6 +93,9 @@ static Layout plan_mats(int64_t n, int n64, int n32) {
     off += round_up(tiles128 * 4, 256);
     L.off_tiles32 = off;
     off += round_up(std::max<int64_t>(tiles32, 1) * 4, 256);
+    const int64_t tiles128e = edge_blocks(n) ? edge_ntiles(n) : 0;
+    L.off_tiles128e = off;
+    off += round_up(tiles128e * 4, 256);
     L.off_lanczos = off;
     off += round_up((5 * L.np + 2 * kMaxLanczos) * sizeof(double), 256);
     L.off_state = off;
@@ -101,6 +104,7 @@ static Layout plan_mats(int64_t n, int n64, int n32) {
     L.ntiles64 = (int)tiles64;
     L.ntiles128 = (int)tiles128;
     L.ntiles32 = (int)tiles32;
+    L.ntiles128e = (int)tiles128e;
     L.part_cap = parts;
     return L;
 }
@@ -124,6 +128,7 @@ void Resources::view(const Layout &L, char *mem) {
     tiles64 = (uint32_t *)(mem + L.off_tiles64);
     tiles128 = (uint32_t *)(mem + L.off_tiles128);
     tiles32 = (uint32_t *)(mem + L.off_tiles32);
+    tiles128e = L.ntiles128e > 0 ? (uint32_t *)(mem + L.off_tiles128e) : nullptr;
     st = (DevState *)(mem + L.off_state);
     lanczos = (double *)(mem + L.off_lanczos);
 }
@@ -208,6 +213,20 @@ int Resources::bind(const Layout &L, void *user_mem, size_t user_bytes, hipStrea
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
         e = hipMemcpyAsync(tiles128, t128.data(), t128.size() * 4, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+        std::vector<uint32_t> t128e;
+        if (L.ntiles128e > 0) {
+            const int t = (int)tile_rows(L.n, 128);
+            t128e = upper_tiles(t - 1);
+            for (int q = 0; q < (t + 1) / 2; ++q)
+                t128e.push_back(0x80000000u | ((uint32_t)q << 16) | (uint32_t)(t - 1));
+            if ((int64_t)t128e.size() != L.ntiles128e) {
+                set_error("internal: edge-block list size");
+                return FDM_EHIP;
+            }
+            e = hipMemcpyAsync(tiles128e, t128e.data(), t128e.size() * 4, hipMemcpyHostToDevice,
+                               s);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+        }
         std::vector<uint32_t> t32;
         if (L.ntiles32 > 0) {
             t32 = upper_tiles((int)tile_rows(L.n, 32));
@@ -282,10 +301,26 @@ int choose_tile(int64_t n, int prec, int forced) {
     if (prec == P_F64 || prec == P_F32) return (t128 >= 16 * 256) ? 128 : 64;
     if (prec == P_F16X3 || prec == P_BF16X3) {
         const int64_t t64 = ntiles_for(n, 64);
-        const bool one_wave_128 = t128 <= 2 * 256 && t64 >= 1400;
+        // blocks of the 128-wide launch, with edge blocks where the K extent
+        // ends 64 columns into the last tile column (N = 4000: 496 tiles and
+        // 16 edge blocks, one wave, instead of 528 tiles)
+        const int64_t b128 = edge_blocks(n) ? edge_ntiles(n) : t128;
+        const bool one_wave_128 = b128 <= 2 * 256 && t64 >= 1400;
         return (t128 >= 8 * 256 || one_wave_128) ? 128 : 64;
     }
     return (t128 >= 4 * 256) ? 128 : 64;
+}
+
+// The tile list of edge bt for precision prec: the 128-wide split products
+// staged straight into LDS take the list with edge blocks where there is one.
+static void set_tiles(ProdArgs &a, const Resources *r, int bt, int prec) {
+    a.tiles = (bt == 128) ? r->tiles128 : (bt == 32 ? r->tiles32 : r->tiles64);
+    a.ntiles = (bt == 128) ? r->lay.ntiles128 : (bt == 32 ? r->lay.ntiles32 : r->lay.ntiles64);
+    if (bt == 128 && (prec == P_F16X3 || prec == P_BF16X3) && r->tiles128e != nullptr &&
+        symprod_direct(prec, 128, r->lay.ld)) {
+        a.tiles = r->tiles128e;
+        a.ntiles = r->lay.ntiles128e;
+    }
 }
 
 int Ctx::product(int prec, const void *A, const void *B, const void *E, void *C,
@@ -300,8 +335,7 @@ int Ctx::product(int prec, const void *A, const void *B, const void *E, void *C,
     a.ld = r->lay.ld;
     a.n = (int32_t)n;
     a.kext = (int32_t)round_up(n, kKStep);
-    a.tiles = (bt == 128) ? r->tiles128 : (bt == 32 ? r->tiles32 : r->tiles64);
-    a.ntiles = (bt == 128) ? r->lay.ntiles128 : (bt == 32 ? r->lay.ntiles32 : r->lay.ntiles64);
+    set_tiles(a, r, bt, prec);
     for (int k = 0; k < 3; ++k) {
         a.coef[0][k] = c0[k];
         a.coef[1][k] = c1 ? c1[k] : c0[k];
@@ -934,8 +968,7 @@ int Ctx::certify_bounds(const double *Hp, int64_t ldh, DevState *h) {
         a.ld = r->lay.ld;
         a.n = (int32_t)n;
         a.kext = (int32_t)round_up(n, kKStep);
-        a.tiles = (bt == 128) ? r->tiles128 : (bt == 32 ? r->tiles32 : r->tiles64);
-        a.ntiles = (bt == 128) ? r->lay.ntiles128 : (bt == 32 ? r->lay.ntiles32 : r->lay.ntiles64);
+        set_tiles(a, r, bt, P_F16X3);
         a.coef[0][0] = a.coef[1][0] = 1.0;
         a.partials = r->part;
         e = launch_symprod(P_F16X3, bt, a, s);

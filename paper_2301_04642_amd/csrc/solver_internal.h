@@ -23,10 +23,11 @@ struct Layout {
     int n64 = 0, n32 = 0;
     size_t off64 = 0, off32 = 0, off_part = 0, off_tiles64 = 0, off_tiles128 = 0, off_state = 0;
     size_t off_tiles32 = 0;  // 32-wide tile list (small N only, else empty)
+    size_t off_tiles128e = 0; // 128-wide list with edge blocks (edge_blocks(n) only)
     size_t off_lanczos = 0;  // 5 vectors of np doubles + alpha/beta (2 x kMaxLanczos)
     size_t off16 = 0;        // hi/lo 16-bit companions of the FP32 buffers
     size_t bytes = 0;
-    int ntiles64 = 0, ntiles128 = 0, ntiles32 = 0;
+    int ntiles64 = 0, ntiles128 = 0, ntiles32 = 0, ntiles128e = 0;
     int64_t part_cap = 0;
 };
 Layout plan_layout(int64_t n, bool finite, int prec);
@@ -52,6 +53,7 @@ struct Resources {
     uint16_t *x16 = nullptr;
     double *part = nullptr;
     uint32_t *tiles64 = nullptr, *tiles128 = nullptr, *tiles32 = nullptr;
+    uint32_t *tiles128e = nullptr;  // null: no edge-block list
     double *lanczos = nullptr;
     DevState *st = nullptr;
     HostMirror *hm_host = nullptr, *hm_dev = nullptr;

@@ -158,6 +158,36 @@ def test_band_energy(fdm, n):
     assert abs(tr - np.trace(d)) <= 1e-12 * n
 
 
+@pytest.mark.parametrize("n", [4000, 3900])
+def test_edge_block_products(fdm, n):
+    """128-wide split products whose K extent ends 64 columns into the last
+    tile column (round_up(n, 64) = 128 T - 64: T = 32 at n = 4000, the odd
+    T = 31 at n = 3900): that column runs as 256 x 64 edge blocks.  Every
+    entry against the FP64 product of the same operands, exact symmetry, the
+    trace partial sum, and the same result as 64-wide tiles to rounding."""
+    import torch
+    rng = np.random.default_rng(n + 1)
+    x = rng.standard_normal((n, n)) / np.sqrt(n)
+    x = 0.5 * (x + x.T)
+    ref = x @ x
+    X = dev(x)
+    C, C64 = torch.empty_like(X), torch.empty_like(X)
+    for prec in ("fp16x3", "bf16x3"):
+        say("edge-block product", prec, n)
+        tr, f2, _ = fdm.fdm_sym_product(prec, X, X, None, C, 1.0, 0.0, 0.0, tile=128)
+        fdm.fdm_sym_product(prec, X, X, None, C64, 1.0, 0.0, 0.0, tile=64)
+        c, c64 = host(C), host(C64)
+        assert np.array_equal(c, c.T), "result must be exactly symmetric"
+        err = np.abs(c - ref).max()
+        tol = product_tol(prec, x, x)
+        print(f"[report] edge blocks n={n} {prec}: max err {err:.2e} (tol {tol:.2e}), "
+              f"vs 64-wide tiles {np.abs(c - c64).max():.2e}", flush=True)
+        assert err <= tol
+        assert np.abs(c - c64).max() <= tol
+        assert abs(tr - np.trace(c)) <= 1e-9 * (1 + abs(np.trace(c)))
+    del X, C, C64
+
+
 @pytest.mark.parametrize("n", [18000, 18500])
 def test_large_tile128_products_sampled(fdm, n):
     """128-wide products at full size, either side of the padded leading

@@ -104,6 +104,34 @@ def test_alone_equals_mix_wide(fdm):
         srv.close()
 
 
+def test_edge_blocks_in_grouped_ticks(fdm):
+    """FP16x3 requests whose 128-wide products run with edge blocks (N = 4000
+    and 3500) and without (N = 3400) share grouped product launches (finite
+    temperature, 500 K): each served result is bitwise the solve alone."""
+    # finite temperature: long enough (several mu evaluations) to overlap
+    wls = [workloads.standard_workload("uniform", n=n, seed_base=300 + n) for n in (4000, 3400, 3500)]
+    alone = []
+    for wl in wls:
+        say("edge alone", wl.n)
+        D, e, st = fdm.solve(dev(wl.hp), wl.n_occ, wl.kT, 1e-8, "fp16x3")
+        assert st.status == 0
+        alone.append((host(D), e))
+    srv = fdm.Server(budget_bytes=40 << 30, max_active=3, precision="fp16x3")
+    try:
+        ts = [srv.submit(wl.hp, wl.n_occ, wl.kT, 1e-8) for wl in wls]
+        shared = 0
+        for t, wl, (d0, e0) in zip(ts, wls, alone):
+            say("edge mix result", wl.n)
+            rc, d, e, st, times = srv.result(t, wl.n)
+            assert rc == 0
+            assert np.array_equal(d, d0) and e == e0, wl.n
+            shared += st.tick_shared
+        print(f"[report] edge-block mix: {shared} shared steps", flush=True)
+        assert shared > 0
+    finally:
+        srv.close()
+
+
 def test_held_memory_within_budget(fdm):
     """Device blocks held by the server (in use or pooled) never exceed the
     budget over a log-uniform mix of sizes."""

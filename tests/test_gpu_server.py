@@ -115,6 +115,10 @@ def test_edge_blocks_in_grouped_ticks(fdm):
         say("edge alone", wl.n)
         D, e, st = fdm.solve(dev(wl.hp), wl.n_occ, wl.kT, 1e-8, "fp16x3")
         assert st.status == 0
+        d_ref, e_ref, _, _ = reference(wl)
+        print(f"[report] edge alone n={wl.n}: |dE|={abs(e - e_ref):.2e} evals={st.mu_evals}",
+              flush=True)
+        assert abs(e - e_ref) <= 1e-6
         alone.append((host(D), e))
     srv = fdm.Server(budget_bytes=40 << 30, max_active=3, precision="fp16x3")
     try:
